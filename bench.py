@@ -1,0 +1,184 @@
+"""Throughput of the CTU lattice Boltzmann step on one MI355X.
+
+Workload (default): the paper's largest lattice, 6144 x 6144 periodic, a van
+der Waals fluid at T = 0.95 T_c (a = 9/8, b = 1/3), superheated liquid at
+0.95 rho_L with a vapour bubble of radius 60 nodes, tau = 0.7, kappa = 1,
+CTU2, ds = 1, dt = 1/4.  One step = one pass of the fused kernel over the
+whole lattice (moments, equilibrium, van der Waals force with its 25-point
+stencils, BGK, CTU2 advection).  The headline value is the FP32-deviation
+stepper's MLUPS; the FP64 stepper runs on the same input for the speedup
+and for the rho/u error of the FP32 storage.
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_LUP = {"f32": 128.0, "f64": 256.0}  # read + write 16 distributions once
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for n in ("lbm_kernels.hip", "lbm_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1802_01272_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(kernel_key)
+    if not entry or entry.get("source_hash") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline(workload, rho, ux, uy, budget_s=12.0, rows=256, max_steps=20):
+    """The oracle (FP64 CPU reference, OpenMP) timed on a band of `rows` full
+    rows of the workload's initial state (periodic), one step at a time until
+    about budget_s seconds of work."""
+    import numpy as np
+    import oracle as o
+    p = o.Params(Lx=workload.Lx, Ly=rows, ds=workload.ds, dt=workload.dt, tau=workload.tau, T=workload.T,
+                 a=workload.a, b=workload.b, kappa=workload.kappa, scheme=workload.scheme,
+                 regularize=workload.regularize)
+    j0 = (workload.Ly - rows) // 2
+    f = o.init(p, np.ascontiguousarray(rho[j0:j0 + rows]), np.ascontiguousarray(ux[j0:j0 + rows]),
+               np.ascontiguousarray(uy[j0:j0 + rows]))
+    o.step(p, f)  # first touch / warm-up
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < max_steps:
+        f = o.step(p, f)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(p.Lx * p.Ly * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": o.num_threads(),
+            "kind": "oracle",
+            "sample": "%d x %d band of the workload's initial state (periodic), %d steps, FP64" % (p.Lx, rows, steps)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--L", type=int, default=6144)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the lattice is advanced on a single device; "
+              "--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1802_01272_amd import inputs as I
+    from paper_1802_01272_amd import lbm
+
+    torch.cuda.set_device(0)
+    w = I.large_lattice(args.L)
+    rho, ux, uy = w.fields()
+    nodes = w.Lx * w.Ly
+    results = {}
+    runs = {}
+    for name, prec in (("f32", lbm.FP32_DEV), ("f64", lbm.FP64)):
+        if name == "f64" and args.fp32_only:
+            continue
+        p = lbm.Params.from_workload(w, precision=prec)
+        launch = None if args.no_autotune else lbm.autotune(p, steps_per_trial=3)
+        run = lbm.Run(p, rho, ux, uy)
+        if launch:
+            run.set_launch(*launch)
+        run.step(args.warmup)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        run.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        per = ms / args.steps
+        results[name] = {"ms_per_step": per, "mlups": nodes / (per * 1e-3) / 1e6, "wall_s": wall,
+                         "launch": run.get_launch()}
+        print("[bench] %s: %.4f ms/step, %.1f MLUPS, launch %s" % (name, per, results[name]["mlups"],
+                                                                   results[name]["launch"]),
+              file=sys.stderr, flush=True)
+        runs[name] = run
+
+    # error of the FP32-deviation storage against the FP64 stepper after the same steps
+    err = None
+    if "f64" in runs:
+        r32, x32, y32 = runs["f32"].moments_device()
+        r64, x64, y64 = runs["f64"].moments_device()
+        umax = torch.sqrt(x64 ** 2 + y64 ** 2).max().clamp_min(1e-300)
+        du = torch.sqrt((x32 - x64) ** 2 + (y32 - y64) ** 2)
+        drho = ((r32 - r64).abs() / r64.abs())
+        err = {"rho_max_rel": float(drho.max()), "rho_rms_rel": float(drho.pow(2).mean().sqrt()),
+               "u_max_rel": float(du.max() / umax), "u_rms_rel": float(du.pow(2).mean().sqrt() / umax),
+               "steps": args.warmup + args.steps, "against": "FP64 GPU stepper, same input"}
+        del r32, x32, y32, r64, x64, y64
+
+    f32 = results["f32"]
+    achieved = BYTES_PER_LUP["f32"] * nodes / (f32["ms_per_step"] * 1e-3) / 1e9
+    line = {
+        "metric": "MLUPS + % HBM roofline, FP32-deviation vs FP64 stepper at stated rho/u error",
+        "value": round(f32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "Lx": w.Lx, "Ly": w.Ly, "T_over_Tc": w.T, "rho_ext": round(w.rho_ext, 6),
+                   "bubble_radius": w.radius, "tau": w.tau, "kappa": w.kappa, "scheme": "CTU2",
+                   "storage": "FP32 f - w rho_ref", "rho_ref": round(w.rho_ref, 6), "launch": list(f32["launch"])},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic("step_fp32dev_ctu2_%d" % w.Lx)},
+    }
+    if "f64" in results:
+        f64 = results["f64"]
+        ach64 = BYTES_PER_LUP["f64"] * nodes / (f64["ms_per_step"] * 1e-3) / 1e9
+        line["fp64"] = {"mlups": round(f64["mlups"], 1), "ms_per_step": round(f64["ms_per_step"], 5),
+                        "achieved_GBs": round(ach64, 1), "frac": round(ach64 / PEAK_HBM_GBS, 4),
+                        "launch": list(f64["launch"])}
+        line["speedup_fp32dev_over_fp64"] = round(f64["ms_per_step"] / f32["ms_per_step"], 3)
+    if err:
+        line["error_fp32dev"] = err
+    for r in runs.values():
+        r.close()
+    del runs
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, rho, ux, uy)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

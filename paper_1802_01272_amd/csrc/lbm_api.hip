@@ -1,0 +1,859 @@
+// lbm_api.hip -- host side of the C ABI declared in include/lbm.h:
+// parameter validation, workspace carving, coefficient tables, launches,
+// diagnostics, the launch-shape autotuner and batched runs with HIP graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_error;
+
+lbm_status fail(lbm_status s, const std::string& msg)
+{
+    g_error = msg;
+    return s;
+}
+
+lbm_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool is_finite_d(double v) { return std::isfinite(v); }
+
+// f^eq of Eq. (herfeq) on the host, used for the wall ghost rows.
+double feq_host(int k, double T, double rho, double ux, double uy)
+{
+    const double cx = xi_x(k), cy = xi_y(k);
+    const double xu = cx * ux + cy * uy, u2 = ux * ux + uy * uy, x2 = cx * cx + cy * cy;
+    return weight(k) * rho
+         * (1.0 + xu + 0.5 * (xu * xu - u2 + (T - 1.0) * (x2 - 2.0))
+            + xu / 6.0 * (xu * xu - 3.0 * u2 + 3.0 * (T - 1.0) * (x2 - 4.0)));
+}
+
+lbm_status validate(const lbm_params* p)
+{
+    if (!p) return fail(LBM_EINVAL, "null parameters");
+    if (p->Lx < 1 || p->Ly < 1) return fail(LBM_EINVAL, "Lx and Ly must be >= 1");
+    // one distribution plane must stay below 4 GiB (32-bit byte offsets)
+    if ((int64_t)p->Lx * (int64_t)p->Ly > (int64_t)1 << 29)
+        return fail(LBM_EINVAL, "Lx * Ly must not exceed 2^29 nodes");
+    const double vals[] = {p->ds, p->dt, p->tau, p->T, p->a, p->b, p->kappa, p->rho_ref, p->u_wall, p->rho_wall};
+    for (double v : vals)
+        if (!is_finite_d(v)) return fail(LBM_EINVAL, "parameters must be finite");
+    if (p->ds <= 0 || p->dt <= 0) return fail(LBM_EINVAL, "ds and dt must be > 0");
+    if (p->tau <= 0) return fail(LBM_EINVAL, "tau must be > 0");
+    if (p->T <= 0) return fail(LBM_EINVAL, "T must be > 0");
+    if (p->a < 0 || p->b < 0 || p->kappa < 0) return fail(LBM_EINVAL, "a, b and kappa must be >= 0");
+    if (p->scheme != 1 && p->scheme != 2) return fail(LBM_EINVAL, "scheme must be 1 (CTU1) or 2 (CTU2)");
+    if (p->regularize != 0 && p->regularize != 1) return fail(LBM_EINVAL, "regularize must be 0 or 1");
+    if (p->precision != LBM_FP64 && p->precision != LBM_FP32_DEV)
+        return fail(LBM_EINVAL, "precision must be LBM_FP64 or LBM_FP32_DEV");
+    if (p->precision == LBM_FP32_DEV && p->rho_ref <= 0)
+        return fail(LBM_EINVAL, "rho_ref must be > 0 for FP32 deviation storage");
+    if (p->bc_y != LBM_PERIODIC && p->bc_y != LBM_SHEAR_WALLS) return fail(LBM_EINVAL, "bc_y must be 0 or 1");
+    if (p->bc_y == LBM_SHEAR_WALLS) {
+        if (p->rho_wall <= 0 || (p->b > 0 && p->b * p->rho_wall >= 1.0))
+            return fail(LBM_EINVAL, "rho_wall must lie in (0, 1/b)");
+    }
+    // CFL condition of the CTU schemes: max_k |xi_k,alpha| dt <= ds
+    if (QL * p->dt > p->ds * (1.0 + 1e-12))
+        return fail(LBM_ECFL, "CFL violated: dt * sqrt(3 + sqrt 6) must not exceed ds");
+    return LBM_OK;
+}
+
+template <typename R>
+void fill_coef(const lbm_params* p, StepCoef<R>& c)
+{
+    std::memset(&c, 0, sizeof(c));
+    const double nu = p->dt / p->ds;
+    const double rho0 = (p->precision == LBM_FP32_DEV) ? p->rho_ref : 0.0;
+    const double q[2] = {QS, QL};
+    for (int mx = 0; mx < 2; ++mx) {
+        const double ax = nu * q[mx], k2x = q[mx] * (1 - ax);
+        c.a[mx] = (R)ax;
+        for (int my = 0; my < 2; ++my) {
+            const double ay = nu * q[my], k2y = q[my] * (1 - ay);
+            c.ab[mx][my] = (R)(ax * ay);
+            c.xs1[mx][my] = (R)(-nu * (1 - ay) * k2x);
+            c.xs2[mx][my] = (R)(-nu * ay * k2x);
+            c.ys1[mx][my] = (R)(-nu * (1 - ax) * k2y);
+            c.ys2[mx][my] = (R)(-nu * ax * k2y);
+        }
+    }
+    double rlo = 0, rhi = 0;
+    for (int k = 0; k < 16; ++k) {
+        const double lo = feq_host(k, p->T, p->rho_wall, -p->u_wall, 0.0);
+        const double hi = feq_host(k, p->T, p->rho_wall, +p->u_wall, 0.0);
+        rlo += lo;
+        rhi += hi;
+        c.ghost_lo[k] = (R)(lo - weight(k) * rho0);
+        c.ghost_hi[k] = (R)(hi - weight(k) * rho0);
+    }
+    c.ghost_rho_lo = rlo;
+    c.ghost_rho_hi = rhi;
+    c.rho0 = rho0;
+    c.T = p->T;
+    c.Tm1 = p->T - 1.0;
+    c.a_vdw = p->a;
+    c.b_vdw = p->b;
+    c.kappa_ds = p->kappa / p->ds;
+    c.inv_ds = 1.0 / p->ds;
+    c.inv_6ds2 = 1.0 / (6.0 * p->ds * p->ds);
+    c.dt_tau = p->dt / p->tau;
+    c.dt = p->dt;
+    c.walls = p->bc_y == LBM_SHEAR_WALLS ? 1 : 0;
+}
+
+size_t storage_bytes(const lbm_params* p) { return p->precision == LBM_FP32_DEV ? 4 : 8; }
+
+// Workspace layout of one run (offsets in bytes, all 256-aligned):
+//   [coef (fp32 + fp64 tables)] [reduction partials + result] [field 0] [field 1]
+constexpr size_t COEF_BYTES = 8192;
+static_assert(sizeof(StepCoef<double>) + sizeof(StepCoef<float>) + 2 * ALIGN <= COEF_BYTES, "coef region");
+constexpr size_t RED_BYTES = (size_t)(REDUCE_MAX_BLOCKS + 1) * REDUCE_VALUES * sizeof(double);
+
+size_t field_bytes(const lbm_params* p) { return align_up((size_t)16 * p->Lx * p->Ly * storage_bytes(p)); }
+
+size_t run_bytes(const lbm_params* p)
+{
+    return COEF_BYTES + align_up(RED_BYTES) + 2 * field_bytes(p);
+}
+
+// default launch shape: enough wavefronts to fill 256 CUs x 4 SIMDs a few times over
+Launch default_launch(const lbm_params* p)
+{
+    const int nstrips = (p->Lx + STRIP - 1) / STRIP;
+    int rows = 64;
+    while (rows > 8 && (int64_t)nstrips * ((p->Ly + rows - 1) / rows) < 4096) rows /= 2;
+    return Launch{rows, 2};
+}
+
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int, int, int, int>, Launch> g_tuned;  // (Lx, Ly, precision, scheme, regularize)
+
+}  // namespace
+
+struct lbm_run {
+    lbm_params p;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* coef = nullptr;        // StepCoef<R> for the storage precision
+    double* red = nullptr;       // reduction partials; result in the last REDUCE_VALUES slots
+    char* field[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t step = 0;
+    Launch launch{64, 2};
+    lbm_batch* batch = nullptr;  // non-null for a borrowed batch member
+};
+
+struct lbm_batch {
+    int32_t n = 0;
+    int precision = 0, scheme = 2, regularize = 0;
+    std::vector<lbm_run> runs;
+    void* d_runs = nullptr;   // BatchRun<R>[n]
+    void* d_coefs = nullptr;  // StepCoef<R>[n]
+    BatchItem* d_items = nullptr;
+    int32_t nitems = 0;
+    int cur = 0;
+    int64_t step = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t graph_steps = 0;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+template <typename R>
+StepCoef<R>* coef_of(lbm_run* r) { return static_cast<StepCoef<R>*>(r->coef); }
+
+template <typename R>
+lbm_status upload_coef(lbm_run* r, hipStream_t s)
+{
+    StepCoef<R> c;
+    fill_coef<R>(&r->p, c);
+    HIP_TRY(hipMemcpyAsync(r->coef, &c, sizeof(c), hipMemcpyHostToDevice, s), "upload coefficients");
+    HIP_TRY(hipStreamSynchronize(s), "upload coefficients");
+    return LBM_OK;
+}
+
+lbm_status carve(const lbm_params* p, void* d_ws, size_t ws_bytes, lbm_run* r)
+{
+    if (!d_ws) return fail(LBM_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(d_ws) % ALIGN) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < run_bytes(p)) return fail(LBM_ENOMEM, "workspace smaller than lbm_workspace_bytes()");
+    r->p = *p;
+    r->ws = static_cast<char*>(d_ws);
+    r->ws_bytes = ws_bytes;
+    r->coef = r->ws;
+    r->red = reinterpret_cast<double*>(r->ws + COEF_BYTES);
+    r->field[0] = r->ws + COEF_BYTES + align_up(RED_BYTES);
+    r->field[1] = r->field[0] + field_bytes(p);
+    r->cur = 0;
+    r->step = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tuned.find({p->Lx, p->Ly, p->precision, p->scheme, p->regularize});
+        r->launch = (it != g_tuned.end()) ? it->second : default_launch(p);
+    }
+    return LBM_OK;
+}
+
+lbm_status upload_coef_any(lbm_run* r, hipStream_t s)
+{
+    return r->p.precision == LBM_FP32_DEV ? upload_coef<float>(r, s) : upload_coef<double>(r, s);
+}
+
+int64_t nodes(const lbm_run* r) { return (int64_t)r->p.Lx * r->p.Ly; }
+
+template <typename R>
+RunView<R> view(lbm_run* r)
+{
+    RunView<R> v;
+    v.f_in = reinterpret_cast<const R*>(r->field[r->cur]);
+    v.f_out = reinterpret_cast<R*>(r->field[r->cur ^ 1]);
+    v.coef = coef_of<R>(r);
+    v.Lx = r->p.Lx;
+    v.Ly = r->p.Ly;
+    v.rows = r->launch.rows_per_wave;
+    v.nstrips = (r->p.Lx + STRIP - 1) / STRIP;
+    v.plane = nodes(r);
+    return v;
+}
+
+lbm_status step_once(lbm_run* r, hipStream_t s)
+{
+    hipError_t e;
+    if (r->p.precision == LBM_FP32_DEV)
+        e = launch_step<float>(view<float>(r), r->p.scheme, r->p.regularize, r->launch.waves_per_group, s);
+    else
+        e = launch_step<double>(view<double>(r), r->p.scheme, r->p.regularize, r->launch.waves_per_group, s);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    r->cur ^= 1;
+    r->step += 1;
+    return LBM_OK;
+}
+
+lbm_status init_common(const lbm_params* p, void* d_ws, size_t ws_bytes, void* stream, const double* rho,
+                       const double* ux, const double* uy, bool host, lbm_run** out)
+{
+    if (!out) return fail(LBM_EINVAL, "null output handle");
+    *out = nullptr;
+    lbm_status st = validate(p);
+    if (st != LBM_OK) return st;
+    if (!rho || !ux || !uy) return fail(LBM_EINVAL, "null initial fields");
+    const int64_t n = (int64_t)p->Lx * p->Ly;
+    if (host) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (!is_finite_d(rho[i]) || !is_finite_d(ux[i]) || !is_finite_d(uy[i]))
+                return fail(LBM_EINVAL, "initial fields must be finite");
+            if (rho[i] <= 0 || (p->b > 0 && p->b * rho[i] >= 1.0))
+                return fail(LBM_EINVAL, "initial density must lie in (0, 1/b)");
+        }
+    }
+    lbm_run* r = new (std::nothrow) lbm_run();
+    if (!r) return fail(LBM_EINVAL, "out of host memory");
+    st = carve(p, d_ws, ws_bytes, r);
+    if (st != LBM_OK) {
+        delete r;
+        return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = upload_coef_any(r, s);
+    if (st != LBM_OK) {
+        delete r;
+        return st;
+    }
+    const double *d_rho = rho, *d_ux = ux, *d_uy = uy;
+    if (host) {
+        // stage the three host arrays in the second field buffer (>= 24 bytes per node)
+        double* stage = reinterpret_cast<double*>(r->field[1]);
+        hipError_t e = hipMemcpyAsync(stage, rho, n * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(stage + n, ux, n * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(stage + 2 * n, uy, n * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            delete r;
+            return hip_fail(e, "upload initial fields");
+        }
+        d_rho = stage;
+        d_ux = stage + n;
+        d_uy = stage + 2 * n;
+    }
+    hipError_t e = (p->precision == LBM_FP32_DEV)
+                       ? launch_init<float>(reinterpret_cast<float*>(r->field[0]), coef_of<float>(r), d_rho, d_ux, d_uy, n, s)
+                       : launch_init<double>(reinterpret_cast<double*>(r->field[0]), coef_of<double>(r), d_rho, d_ux, d_uy, n, s);
+    if (e == hipSuccess && host) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete r;
+        return hip_fail(e, "init");
+    }
+    *out = r;
+    return LBM_OK;
+}
+
+// FP64 staging buffer for one plane / one moment field: the non-current field
+lbm_status moments_to(lbm_run* r, double* rho, double* ux, double* uy, hipStream_t s)
+{
+    const int64_t n = nodes(r);
+    hipError_t e = (r->p.precision == LBM_FP32_DEV)
+                       ? launch_moments<float>(reinterpret_cast<const float*>(r->field[r->cur]), coef_of<float>(r), rho, ux, uy, n, s)
+                       : launch_moments<double>(reinterpret_cast<const double*>(r->field[r->cur]), coef_of<double>(r), rho, ux, uy, n, s);
+    if (e != hipSuccess) return hip_fail(e, "moments");
+    return LBM_OK;
+}
+
+lbm_status get_plane(lbm_run* r, int k, double* d_out, hipStream_t s)
+{
+    const int64_t n = nodes(r);
+    hipError_t e = (r->p.precision == LBM_FP32_DEV)
+                       ? launch_get_plane<float>(reinterpret_cast<const float*>(r->field[r->cur]), coef_of<float>(r), k, d_out, n, s)
+                       : launch_get_plane<double>(reinterpret_cast<const double*>(r->field[r->cur]), coef_of<double>(r), k, d_out, n, s);
+    if (e != hipSuccess) return hip_fail(e, "get_f");
+    return LBM_OK;
+}
+
+lbm_status set_plane(lbm_run* r, int k, const double* d_in, hipStream_t s)
+{
+    const int64_t n = nodes(r);
+    hipError_t e = (r->p.precision == LBM_FP32_DEV)
+                       ? launch_set_plane<float>(reinterpret_cast<float*>(r->field[r->cur]), coef_of<float>(r), k, d_in, n, s)
+                       : launch_set_plane<double>(reinterpret_cast<double*>(r->field[r->cur]), coef_of<double>(r), k, d_in, n, s);
+    if (e != hipSuccess) return hip_fail(e, "set_f");
+    return LBM_OK;
+}
+
+void derive_stats(const lbm_run* r, const double* v, lbm_stats* o)
+{
+    std::memset(o, 0, sizeof(*o));
+    o->mass = v[0];
+    o->mom_x = v[1];
+    o->mom_y = v[2];
+    o->n_bubble = (int64_t)std::llround(v[3]);
+    o->n_nonfinite = (int64_t)std::llround(v[4]);
+    o->sx = v[5];
+    o->sy = v[6];
+    o->sxx = v[7];
+    o->sxy = v[8];
+    o->syy = v[9];
+    const double N = (double)o->n_bubble;
+    o->A_rel = N / ((double)r->p.Lx * (double)r->p.Ly);
+    o->R_eq = r->p.ds * std::sqrt(N / M_PI);
+    if (o->n_bubble > 0) {
+        o->cx = o->sx / N + 0.5 * (r->p.Lx - 1);
+        o->cy = o->sy / N + 0.5 * (r->p.Ly - 1);
+        const double mx = o->sx / N, my = o->sy / N;
+        o->Txx = o->sxx / N - mx * mx;
+        o->Txy = o->sxy / N - mx * my;
+        o->Tyy = o->syy / N - my * my;
+        const double h = 0.5 * (o->Txx + o->Tyy);
+        const double q = std::sqrt(0.25 * (o->Txx - o->Tyy) * (o->Txx - o->Tyy) + o->Txy * o->Txy);
+        const double lmax = h + q, lmin = std::max(h - q, 0.0);
+        o->a = 2.0 * std::sqrt(std::max(lmax, 0.0));
+        o->b = 2.0 * std::sqrt(lmin);
+        o->D = (o->a + o->b) > 0 ? (o->a - o->b) / (o->a + o->b) : 0.0;
+        o->theta = 0.5 * std::atan2(2.0 * o->Txy, o->Txx - o->Tyy);
+    }
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+
+extern "C" {
+
+const char* lbm_version(void) { return "paper_1802_01272_amd lbm 0.1 (gfx950)"; }
+
+const char* lbm_last_error(void) { return g_error.c_str(); }
+
+lbm_status lbm_validate(const lbm_params* p) { return validate(p); }
+
+size_t lbm_workspace_bytes(const lbm_params* p)
+{
+    if (validate(p) != LBM_OK) return 0;
+    return run_bytes(p);
+}
+
+lbm_status lbm_init(const lbm_params* p, void* d_ws, size_t ws_bytes, void* stream, const double* h_rho0,
+                    const double* h_ux0, const double* h_uy0, lbm_run** out)
+{
+    return init_common(p, d_ws, ws_bytes, stream, h_rho0, h_ux0, h_uy0, true, out);
+}
+
+lbm_status lbm_init_device(const lbm_params* p, void* d_ws, size_t ws_bytes, void* stream, const double* d_rho0,
+                           const double* d_ux0, const double* d_uy0, lbm_run** out)
+{
+    return init_common(p, d_ws, ws_bytes, stream, d_rho0, d_ux0, d_uy0, false, out);
+}
+
+lbm_status lbm_attach(const lbm_params* p, void* d_ws, size_t ws_bytes, int64_t step, lbm_run** out)
+{
+    if (!out) return fail(LBM_EINVAL, "null output handle");
+    *out = nullptr;
+    lbm_status st = validate(p);
+    if (st != LBM_OK) return st;
+    if (step < 0) return fail(LBM_EINVAL, "step must be >= 0");
+    lbm_run* r = new (std::nothrow) lbm_run();
+    if (!r) return fail(LBM_EINVAL, "out of host memory");
+    st = carve(p, d_ws, ws_bytes, r);
+    if (st == LBM_OK) st = upload_coef_any(r, nullptr);
+    if (st != LBM_OK) {
+        delete r;
+        return st;
+    }
+    r->cur = (int)(step & 1);
+    r->step = step;
+    *out = r;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_run* run, int64_t nsteps, void* stream)
+{
+    if (!run) return fail(LBM_EINVAL, "null run");
+    if (run->batch) return fail(LBM_ESTATE, "runs of a batch advance with lbm_batch_step");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int64_t i = 0; i < nsteps; ++i) {
+        lbm_status st = step_once(run, s);
+        if (st != LBM_OK) return st;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_step_timed(lbm_run* run, int64_t nsteps, void* stream, double* ms)
+{
+    if (!run || !ms) return fail(LBM_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a), "event");
+    HIP_TRY(hipEventCreate(&b), "event");
+    hipError_t e = hipEventRecord(a, s);
+    lbm_status st = (e == hipSuccess) ? lbm_step(run, nsteps, stream) : hip_fail(e, "event record");
+    if (st == LBM_OK) {
+        e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float f = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+        if (e != hipSuccess) st = hip_fail(e, "event timing");
+        *ms = f;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
+}
+
+int64_t lbm_step_count(const lbm_run* run) { return run ? run->step : -1; }
+
+lbm_status lbm_moments_device(lbm_run* run, double* d_rho, double* d_ux, double* d_uy, void* stream)
+{
+    if (!run || !d_rho || !d_ux || !d_uy) return fail(LBM_EINVAL, "null argument");
+    return moments_to(run, d_rho, d_ux, d_uy, static_cast<hipStream_t>(stream));
+}
+
+lbm_status lbm_moments(lbm_run* run, double* h_rho, double* h_ux, double* h_uy, void* stream)
+{
+    if (!run || !h_rho || !h_ux || !h_uy) return fail(LBM_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = nodes(run);
+    // the non-current field buffer holds >= 24 bytes per node
+    double* stage = reinterpret_cast<double*>(run->field[run->cur ^ 1]);
+    lbm_status st = moments_to(run, stage, stage + n, stage + 2 * n, s);
+    if (st != LBM_OK) return st;
+    HIP_TRY(hipMemcpyAsync(h_rho, stage, n * sizeof(double), hipMemcpyDeviceToHost, s), "moments download");
+    HIP_TRY(hipMemcpyAsync(h_ux, stage + n, n * sizeof(double), hipMemcpyDeviceToHost, s), "moments download");
+    HIP_TRY(hipMemcpyAsync(h_uy, stage + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, s), "moments download");
+    HIP_TRY(hipStreamSynchronize(s), "moments download");
+    return LBM_OK;
+}
+
+lbm_status lbm_get_f_device(lbm_run* run, double* d_f, void* stream)
+{
+    if (!run || !d_f) return fail(LBM_EINVAL, "null argument");
+    const int64_t n = nodes(run);
+    for (int k = 0; k < 16; ++k) {
+        lbm_status st = get_plane(run, k, d_f + k * n, static_cast<hipStream_t>(stream));
+        if (st != LBM_OK) return st;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_f_device(lbm_run* run, const double* d_f, void* stream)
+{
+    if (!run || !d_f) return fail(LBM_EINVAL, "null argument");
+    const int64_t n = nodes(run);
+    for (int k = 0; k < 16; ++k) {
+        lbm_status st = set_plane(run, k, d_f + k * n, static_cast<hipStream_t>(stream));
+        if (st != LBM_OK) return st;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_f(lbm_run* run, double* h_f, void* stream)
+{
+    if (!run || !h_f) return fail(LBM_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = nodes(run);
+    double* stage = reinterpret_cast<double*>(run->field[run->cur ^ 1]);  // one FP64 plane fits
+    for (int k = 0; k < 16; ++k) {
+        lbm_status st = get_plane(run, k, stage, s);
+        if (st != LBM_OK) return st;
+        HIP_TRY(hipMemcpyAsync(h_f + k * n, stage, n * sizeof(double), hipMemcpyDeviceToHost, s), "get_f download");
+        HIP_TRY(hipStreamSynchronize(s), "get_f download");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_f(lbm_run* run, const double* h_f, void* stream)
+{
+    if (!run || !h_f) return fail(LBM_EINVAL, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = nodes(run);
+    double* stage = reinterpret_cast<double*>(run->field[run->cur ^ 1]);
+    for (int k = 0; k < 16; ++k) {
+        HIP_TRY(hipMemcpyAsync(stage, h_f + k * n, n * sizeof(double), hipMemcpyHostToDevice, s), "set_f upload");
+        lbm_status st = set_plane(run, k, stage, s);
+        if (st != LBM_OK) return st;
+        HIP_TRY(hipStreamSynchronize(s), "set_f upload");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_reduce(lbm_run* run, double rho_threshold, lbm_stats* out, void* stream)
+{
+    if (!run || !out) return fail(LBM_EINVAL, "null argument");
+    if (!is_finite_d(rho_threshold)) return fail(LBM_EINVAL, "threshold must be finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* result = run->red + (size_t)REDUCE_MAX_BLOCKS * REDUCE_VALUES;
+    hipError_t e = (run->p.precision == LBM_FP32_DEV)
+                       ? launch_reduce<float>(reinterpret_cast<const float*>(run->field[run->cur]), coef_of<float>(run),
+                                              run->p.Lx, run->p.Ly, rho_threshold, run->red, REDUCE_MAX_BLOCKS, result, s)
+                       : launch_reduce<double>(reinterpret_cast<const double*>(run->field[run->cur]), coef_of<double>(run),
+                                               run->p.Lx, run->p.Ly, rho_threshold, run->red, REDUCE_MAX_BLOCKS, result, s);
+    if (e != hipSuccess) return hip_fail(e, "reduce");
+    double v[REDUCE_VALUES];
+    HIP_TRY(hipMemcpyAsync(v, result, sizeof(v), hipMemcpyDeviceToHost, s), "reduce download");
+    HIP_TRY(hipStreamSynchronize(s), "reduce");
+    derive_stats(run, v, out);
+    if (out->n_nonfinite > 0) return fail(LBM_ENONFINITE, "non-finite distribution values in the state");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per_group)
+{
+    if (!run) return fail(LBM_EINVAL, "null run");
+    if (rows_per_wave < 1) return fail(LBM_EINVAL, "rows_per_wave must be >= 1");
+    if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
+        return fail(LBM_EINVAL, "waves_per_group must be 1, 2 or 4");
+    run->launch = Launch{rows_per_wave, waves_per_group};
+    return LBM_OK;
+}
+
+lbm_status lbm_get_launch(const lbm_run* run, int32_t* rows_per_wave, int32_t* waves_per_group)
+{
+    if (!run || !rows_per_wave || !waves_per_group) return fail(LBM_EINVAL, "null argument");
+    *rows_per_wave = run->launch.rows_per_wave;
+    *waves_per_group = run->launch.waves_per_group;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(const lbm_params* p, void* d_ws, size_t ws_bytes, void* stream, int32_t steps_per_trial,
+                        int32_t* rows_per_wave, int32_t* waves_per_group)
+{
+    if (!rows_per_wave || !waves_per_group) return fail(LBM_EINVAL, "null argument");
+    lbm_status st = validate(p);
+    if (st != LBM_OK) return st;
+    if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    lbm_run r;
+    st = carve(p, d_ws, ws_bytes, &r);
+    if (st == LBM_OK) st = upload_coef_any(&r, s);
+    if (st != LBM_OK) return st;
+    // synthetic state: f^eq of a uniform fluid at the middle of the allowed density range
+    {
+        const double rho_u = (p->b > 0) ? std::min(1.0, 0.5 / p->b) : 1.0;
+        const int64_t n = nodes(&r);
+        double* stage = reinterpret_cast<double*>(r.field[1]);
+        std::vector<double> h(n, rho_u), z(n, 0.0);
+        HIP_TRY(hipMemcpyAsync(stage, h.data(), n * sizeof(double), hipMemcpyHostToDevice, s), "autotune");
+        HIP_TRY(hipMemcpyAsync(stage + n, z.data(), n * sizeof(double), hipMemcpyHostToDevice, s), "autotune");
+        HIP_TRY(hipMemcpyAsync(stage + 2 * n, z.data(), n * sizeof(double), hipMemcpyHostToDevice, s), "autotune");
+        hipError_t e = (p->precision == LBM_FP32_DEV)
+                           ? launch_init<float>(reinterpret_cast<float*>(r.field[0]), coef_of<float>(&r), stage, stage + n, stage + 2 * n, n, s)
+                           : launch_init<double>(reinterpret_cast<double*>(r.field[0]), coef_of<double>(&r), stage, stage + n, stage + 2 * n, n, s);
+        if (e != hipSuccess) return hip_fail(e, "autotune init");
+        HIP_TRY(hipStreamSynchronize(s), "autotune init");
+    }
+    const int rows_c[] = {8, 16, 32, 48, 64, 96, 128, 192, 256};
+    const int wpg_c[] = {1, 2, 4};
+    double best = 1e300;
+    Launch bl = default_launch(p);
+    for (int rows : rows_c) {
+        if (rows > 2 * p->Ly && rows != rows_c[0]) continue;
+        for (int wpg : wpg_c) {
+            r.launch = Launch{rows, wpg};
+            for (int w = 0; w < 2; ++w) {
+                st = step_once(&r, s);
+                if (st != LBM_OK) return st;
+            }
+            double ms = 0;
+            st = lbm_step_timed(&r, steps_per_trial, stream, &ms);
+            if (st != LBM_OK) return st;
+            if (ms < best) {
+                best = ms;
+                bl = r.launch;
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tuned[{p->Lx, p->Ly, p->precision, p->scheme, p->regularize}] = bl;
+    }
+    *rows_per_wave = bl.rows_per_wave;
+    *waves_per_group = bl.waves_per_group;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_run* run)
+{
+    if (run && !run->batch) delete run;
+}
+
+// ---------------------------------------------------------------------------
+// batched runs
+
+}  // extern "C"
+
+extern "C" size_t lbm_batch_workspace_bytes(int32_t n, const lbm_params* params)
+{
+    if (n < 1 || !params) return 0;
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (validate(&params[i]) != LBM_OK) return 0;
+        total += run_bytes(&params[i]);
+    }
+    // tables: runs, coefficient copies, work items
+    size_t items = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t ns = (params[i].Lx + STRIP - 1) / STRIP;
+        items += (size_t)ns * (size_t)params[i].Ly;  // upper bound: one row per wavefront
+    }
+    total += align_up((size_t)n * sizeof(BatchRun<double>)) + align_up((size_t)n * sizeof(StepCoef<double>))
+           + align_up(items * sizeof(BatchItem));
+    return total;
+}
+
+namespace {
+
+template <typename R>
+lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
+{
+    std::vector<BatchRun<R>> runs(b->n);
+    std::vector<StepCoef<R>> coefs(b->n);
+    std::vector<BatchItem> items;
+    for (int i = 0; i < b->n; ++i) {
+        lbm_run& r = b->runs[i];
+        BatchRun<R>& br = runs[i];
+        br.f[0] = reinterpret_cast<R*>(r.field[0]);
+        br.f[1] = reinterpret_cast<R*>(r.field[1]);
+        br.coef = nullptr;
+        br.Lx = r.p.Lx;
+        br.Ly = r.p.Ly;
+        br.rows = r.launch.rows_per_wave;
+        br.nstrips = (r.p.Lx + STRIP - 1) / STRIP;
+        br.plane = nodes(&r);
+        fill_coef<R>(&r.p, coefs[i]);
+        const int nchunks = (r.p.Ly + br.rows - 1) / br.rows;
+        for (int c = 0; c < nchunks; ++c)
+            for (int st = 0; st < br.nstrips; ++st) items.push_back(BatchItem{i, st, c, 0});
+    }
+    char* p = base;
+    b->d_runs = p;
+    p += align_up((size_t)b->n * sizeof(BatchRun<double>));
+    b->d_coefs = p;
+    p += align_up((size_t)b->n * sizeof(StepCoef<double>));
+    b->d_items = reinterpret_cast<BatchItem*>(p);
+    b->nitems = (int32_t)items.size();
+    HIP_TRY(hipMemcpyAsync(b->d_runs, runs.data(), runs.size() * sizeof(BatchRun<R>), hipMemcpyHostToDevice, s), "batch tables");
+    HIP_TRY(hipMemcpyAsync(b->d_coefs, coefs.data(), coefs.size() * sizeof(StepCoef<R>), hipMemcpyHostToDevice, s), "batch tables");
+    HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s), "batch tables");
+    HIP_TRY(hipStreamSynchronize(s), "batch tables");
+    return LBM_OK;
+}
+
+lbm_status batch_launch(lbm_batch* b, hipStream_t s)
+{
+    hipError_t e;
+    if (b->precision == LBM_FP32_DEV)
+        e = launch_batch_step<float>(static_cast<const BatchRun<float>*>(b->d_runs),
+                                     static_cast<const StepCoef<float>*>(b->d_coefs), b->d_items, b->nitems, b->cur,
+                                     b->scheme, b->regularize, 1, s);
+    else
+        e = launch_batch_step<double>(static_cast<const BatchRun<double>*>(b->d_runs),
+                                      static_cast<const StepCoef<double>*>(b->d_coefs), b->d_items, b->nitems, b->cur,
+                                      b->scheme, b->regularize, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "batch step launch");
+    b->cur ^= 1;
+    return LBM_OK;
+}
+
+void batch_advance_members(lbm_batch* b, int64_t nsteps)
+{
+    b->step += nsteps;
+    for (auto& r : b->runs) {
+        r.cur = b->cur;
+        r.step = b->step;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_init(int32_t n, const lbm_params* params, void* d_ws, size_t ws_bytes, void* stream,
+                          const double* const* h_rho0, const double* const* h_ux0, const double* const* h_uy0,
+                          lbm_batch** out)
+{
+    if (!out) return fail(LBM_EINVAL, "null output handle");
+    *out = nullptr;
+    if (n < 1 || !params || !h_rho0 || !h_ux0 || !h_uy0) return fail(LBM_EINVAL, "bad batch arguments");
+    for (int i = 0; i < n; ++i) {
+        lbm_status st = validate(&params[i]);
+        if (st != LBM_OK) return fail(st, "run " + std::to_string(i) + ": " + g_error);
+        if (params[i].precision != params[0].precision || params[i].scheme != params[0].scheme
+            || params[i].regularize != params[0].regularize)
+            return fail(LBM_EINVAL, "all runs of a batch must share precision, scheme and regularize");
+    }
+    const size_t need = lbm_batch_workspace_bytes(n, params);
+    if (!d_ws) return fail(LBM_EINVAL, "null workspace");
+    if (ws_bytes < need) return fail(LBM_ENOMEM, "workspace smaller than lbm_batch_workspace_bytes()");
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return fail(LBM_EINVAL, "out of host memory");
+    b->n = n;
+    b->precision = params[0].precision;
+    b->scheme = params[0].scheme;
+    b->regularize = params[0].regularize;
+    b->runs.resize(n);
+    char* p = static_cast<char*>(d_ws);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+        lbm_run* r = nullptr;
+        lbm_status st = init_common(&params[i], p, run_bytes(&params[i]), stream, h_rho0[i], h_ux0[i], h_uy0[i], true, &r);
+        if (st != LBM_OK) {
+            delete b;
+            return fail(st, "run " + std::to_string(i) + ": " + g_error);
+        }
+        b->runs[i] = *r;
+        delete r;
+        b->runs[i].batch = b;
+        p += run_bytes(&params[i]);
+    }
+    lbm_status st = (b->precision == LBM_FP32_DEV) ? batch_tables<float>(b, p, s) : batch_tables<double>(b, p, s);
+    if (st != LBM_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int32_t graph_steps, void* stream)
+{
+    if (!b) return fail(LBM_EINVAL, "null batch");
+    if (nsteps < 0 || graph_steps < 0) return fail(LBM_EINVAL, "negative step count");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t done = 0;
+    // a captured graph alternates the two field buffers, so it holds an even
+    // number of steps and is replayed from an even parity only
+    const int32_t gsteps = graph_steps - (graph_steps & 1);
+    if (gsteps > 0) {
+        if (b->exec && b->graph_steps != gsteps) {
+            (void)hipGraphExecDestroy(b->exec);
+            (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+        }
+        while (nsteps - done >= gsteps) {
+            if (b->cur != 0) {
+                lbm_status st = batch_launch(b, s);
+                if (st != LBM_OK) return st;
+                batch_advance_members(b, 1);
+                ++done;
+                continue;
+            }
+            if (!b->exec) {
+                if (!b->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking), "capture stream");
+                HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+                const int saved = b->cur;
+                for (int32_t i = 0; i < gsteps; ++i) {
+                    lbm_status st = batch_launch(b, b->capture_stream);
+                    if (st != LBM_OK) {
+                        hipGraph_t g;
+                        (void)hipStreamEndCapture(b->capture_stream, &g);
+                        if (g) (void)hipGraphDestroy(g);
+                        b->cur = saved;
+                        return st;
+                    }
+                }
+                b->cur = saved;
+                HIP_TRY(hipStreamEndCapture(b->capture_stream, &b->graph), "end capture");
+                HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+                b->graph_steps = gsteps;
+            }
+            HIP_TRY(hipGraphLaunch(b->exec, s), "graph launch");
+            // gsteps is even: the parity is unchanged
+            batch_advance_members(b, gsteps);
+            done += gsteps;
+        }
+    }
+    for (; done < nsteps; ++done) {
+        lbm_status st = batch_launch(b, s);
+        if (st != LBM_OK) return st;
+        batch_advance_members(b, 1);
+    }
+    return LBM_OK;
+}
+
+lbm_run* lbm_batch_run(lbm_batch* b, int32_t r)
+{
+    if (!b || r < 0 || r >= b->n) {
+        g_error = "batch run index out of range";
+        return nullptr;
+    }
+    return &b->runs[r];
+}
+
+void lbm_batch_destroy(lbm_batch* b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// lbm_internal.hpp -- definitions shared by the HIP kernels and the host side
+// of the library (not part of the public ABI in include/lbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Velocity set of Table "roots": Cartesian components are +-QS or +-QL, the
+// roots of He4(x) = x^4 - 6x^2 + 3 (QS = sqrt(3 - sqrt 6), QL = sqrt(3 + sqrt 6)).
+// Group g = k / 4 fixes the magnitudes, s = k % 4 the signs
+// (+,+), (-,+), (-,-), (+,-).
+constexpr double QS = 0.74196378430272585764851359672636;
+constexpr double QL = 2.33441421833897723931751226721036;
+constexpr double W_SS = 0.20622873928263242075822016977941;  // (5 + 2 sqrt 6)/48
+constexpr double W_SL = 0.02083333333333333333333333333333;  // 1/48
+constexpr double W_LL = 0.00210459405070091257511316355392;  // (5 - 2 sqrt 6)/48
+
+__host__ __device__ constexpr double group_qx(int g) { return (g == 0 || g == 2) ? QS : QL; }
+__host__ __device__ constexpr double group_qy(int g) { return (g < 2) ? QS : QL; }
+__host__ __device__ constexpr double group_w(int g) { return g == 0 ? W_SS : (g == 3 ? W_LL : W_SL); }
+__host__ __device__ constexpr int sign_x(int k) { return ((k & 3) == 0 || (k & 3) == 3) ? 1 : -1; }
+__host__ __device__ constexpr int sign_y(int k) { return ((k & 3) < 2) ? 1 : -1; }
+__host__ __device__ constexpr double xi_x(int k) { return sign_x(k) * group_qx(k >> 2); }
+__host__ __device__ constexpr double xi_y(int k) { return sign_y(k) * group_qy(k >> 2); }
+__host__ __device__ constexpr double weight(int k) { return group_w(k >> 2); }
+
+// Output columns per wavefront: 64 lanes minus a 2-lane halo on each side.
+constexpr int WAVE = 64;
+constexpr int HALO = 2;
+constexpr int STRIP = WAVE - 2 * HALO;
+
+// ---------------------------------------------------------------------------
+// Per-run coefficients, prepared on the host in the storage precision R and
+// read by the kernels through uniform (scalar) loads.
+template <typename R>
+struct StepCoef {
+    // advection, in the storage precision R, indexed by the magnitude class m
+    // of a velocity component (0: |xi| = QS, 1: |xi| = QL); nu = dt/ds
+    R a[2];        // nu |xi|                            (CTU1 increment weights)
+    R ab[2][2];    // a[mx] * a[my]
+    // CTU2: the limited corrections are kept unscaled, X' = S^x / k2[mx] and
+    // Y' = S^y / k2[my] with k2 = |xi| (1 - nu |xi|); the scales are folded
+    // into the blend weights of their differences, indexed [mx][my]:
+    R xs1[2][2];   // -nu (1 - nu |xi_y|) k2[mx]   weight of dX at the output row
+    R xs2[2][2];   // -nu  nu |xi_y|      k2[mx]   weight of dX at the row upwind in y
+    R ys1[2][2];   // -nu (1 - nu |xi_x|) k2[my]   weight of dY at the output column
+    R ys2[2][2];   // -nu  nu |xi_x|      k2[my]   weight of dY at the column upwind in x
+    R ghost_lo[16], ghost_hi[16];          // stored values of the two wall ghost-row states
+    // node-local terms, always FP64
+    double rho0;        // rho_ref (deviation storage) or 0
+    double T, Tm1;      // T and T - 1
+    double a_vdw, b_vdw;
+    double kappa_ds;    // kappa / ds
+    double inv_ds;      // 1 / ds
+    double inv_6ds2;    // 1 / (6 ds^2)
+    double dt_tau;      // dt / tau
+    double dt;
+    double ghost_rho_lo, ghost_rho_hi;  // density of the ghost rows (sum of their f)
+    int32_t walls;
+    int32_t pad_;
+};
+
+// magnitude class of the x / y component of velocity k
+__host__ __device__ constexpr int mag_x(int k) { return ((k >> 2) == 1 || (k >> 2) == 3) ? 1 : 0; }
+__host__ __device__ constexpr int mag_y(int k) { return (k >> 2) >= 2 ? 1 : 0; }
+
+// One run as the step kernels see it.
+template <typename R>
+struct RunView {
+    const R* f_in;
+    R* f_out;
+    const StepCoef<R>* coef;
+    int32_t Lx, Ly;
+    int32_t rows;       // rows per wavefront
+    int32_t nstrips;    // wavefront strips along x
+    int64_t plane;      // Lx * Ly
+};
+
+// Work item of the batched launch.
+struct BatchItem {
+    int32_t run, strip, chunk, pad_;
+};
+
+template <typename R>
+struct BatchRun {
+    R* f[2];
+    const StepCoef<R>* coef;
+    int32_t Lx, Ly;
+    int32_t rows, nstrips;
+    int64_t plane;
+};
+
+// Launch shape of the step kernel.
+struct Launch {
+    int32_t rows_per_wave;
+    int32_t waves_per_group;
+};
+
+// Host launchers (lbm_kernels.hip).
+template <typename R>
+hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int waves_per_group,
+                       hipStream_t s);
+template <typename R>
+hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coefs,
+                             const BatchItem* d_items, int32_t nitems, int32_t cur, int scheme,
+                             int regularize, int waves_per_group, hipStream_t s);
+template <typename R>
+hipError_t launch_init(R* f, const StepCoef<R>* coef, const double* rho, const double* ux,
+                       const double* uy, int64_t n, hipStream_t s);
+template <typename R>
+hipError_t launch_moments(const R* f, const StepCoef<R>* coef, double* rho, double* ux, double* uy,
+                          int64_t n, hipStream_t s);
+template <typename R>
+hipError_t launch_get_plane(const R* f, const StepCoef<R>* coef, int k, double* out, int64_t n,
+                            hipStream_t s);
+template <typename R>
+hipError_t launch_set_plane(R* f, const StepCoef<R>* coef, int k, const double* in, int64_t n,
+                            hipStream_t s);
+template <typename R>
+hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_t Ly,
+                         double threshold, double* partials, int32_t max_blocks, double* result,
+                         hipStream_t s);
+
+constexpr int REDUCE_VALUES = 10;
+constexpr int REDUCE_MAX_BLOCKS = 2048;
+
+}  // namespace lbm

@@ -1,0 +1,749 @@
+// lbm_kernels.hip -- gfx950 kernels of the CTU lattice Boltzmann stepper.
+//
+// One time step of the 16-velocity, third-order isothermal lattice Boltzmann
+// model of Sofonea et al. (arXiv:1802.01272):
+//   f_k^{n+1} = A_k(f^n) - (dt/tau)(f_k - f_k^eq) + dt F_k        (Sec. II C 2)
+// with f^eq of Eq. (herfeq), F_k of Eq. (herforce), the acceleration of
+// Eq. (eder) from 25-point stencils (Sec. II B), optional regularization
+// (Eq. ereg) and CTU1 (Eq. ctueq) or CTU2 (Sec. II C 2) advection A_k.
+//
+// Design (MI355X / CDNA4):
+//  * A wavefront owns a strip of 64 consecutive columns (60 written, 2 halo
+//    columns each side, periodic in x) and marches up a chunk of rows.  Every
+//    x-neighbour access is a DPP wave shift (lane i reads lane i -+ 1); every
+//    y-neighbour is a register carried from earlier rows.  No LDS, no
+//    barriers: each wavefront is independent.
+//  * Each loaded row is used for everything at once: its density feeds the
+//    force stencils two rows behind, its f_k feed the upwind differences, and
+//    the output row two rows behind is finished and stored.  Each value of f
+//    is read from HBM once per step (plus the 4-column and 4-row halo) and
+//    written once.
+//  * CTU2 is evaluated in an equivalent rearranged form: the CTU1 bilinear
+//    update (Eq. ctueq) plus, per node, the limited corrections X = S^x and
+//    Y = S^y (division-free MC limiter) computed once per node and blended
+//    with their upwind neighbours.  Up to rounding this equals the paper's
+//    flux-difference form with the transverse R^y index read as
+//    (i + (1 - s_x)/2, j + (1 - s_y)/2) and the S^y ratio taken in R^y.
+//  * Collision and force together are one cubic polynomial in xi with 10
+//    per-node coefficients (both f^eq/w_k and F_k/w_k are cubic in xi); it is
+//    evaluated for the four sign variants of each velocity group through
+//    even/odd parts.
+//  * Storage is FP64, or FP32 deviations d_k = f_k - w_k rho_ref (advection
+//    is linear and preserves constants, so it acts on d_k directly).  The
+//    advective increment A_k(f) - f is formed from upwind differences, so it
+//    is exactly zero on a constant field in any precision, and it is added to
+//    f last.  Node-local arithmetic (moments, stencils, collision and force)
+//    is FP64 in both storage modes: in FP32 its rounding acts as a small
+//    systematic forcing that accumulates step after step.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "lbm_internal.hpp"
+
+namespace lbm {
+namespace {
+
+// ----------------------------------------------------------------------------
+// compile-time loop
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// cross-lane shifts (DPP wave shifts; whole 64-lane wavefront, all lanes active)
+
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i reads lane i-1
+constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i reads lane i+1
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+// value held by the lane of column i-1 / i+1
+template <typename R> __device__ __forceinline__ R from_left(R v) { return dpp<DPP_WAVE_SHR1>(v); }
+template <typename R> __device__ __forceinline__ R from_right(R v) { return dpp<DPP_WAVE_SHL1>(v); }
+// value at column i - s (the upwind neighbour for a velocity of x-sign s)
+template <int S, typename R>
+__device__ __forceinline__ R upwind_x(R v)
+{
+    if constexpr (S > 0) return from_left(v);
+    else return from_right(v);
+}
+
+// minmod(a, b) = median(a, b, 0): 0 when the signs differ, else the smaller one
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+__device__ __forceinline__ double minmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
+
+// MC-limited correction R Psi_MC(R_up / R) = minmod(2R, 2R_up, (R + R_up)/2)
+// (0 for R = 0, no division), returned halved:
+// minmod(minmod(R, R_up), (R + R_up)/4).
+template <typename R>
+__device__ __forceinline__ R mc_half(R r, R ru)
+{
+    return minmod(minmod(r, ru), R(0.25) * (r + ru));
+}
+
+// weights of the 24-neighbour isotropic gradient, by |e|^2
+template <typename R> struct G5W {
+    static constexpr R w1 = R(4.0 / 21.0), w2 = R(4.0 / 45.0), w4 = R(1.0 / 60.0),
+                       w5 = R(2.0 / 315.0), w8 = R(1.0 / 5040.0);
+};
+
+// ----------------------------------------------------------------------------
+// The fused step for one wavefront strip.
+//
+// Rows are processed in order; at iteration t the newest row is r = y0 - 2 + t
+// and the row finished (and stored, for t >= 4) is j = r - 2.  Per velocity,
+// the ring holds f at rows j-1, j, j+1 and the new row j+2.
+
+template <typename R, int SCHEME, bool REG>
+__device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restrict__ fout,
+                                           const StepCoef<R>* __restrict__ C,
+                                           const int Lx, const int Ly, const int64_t plane,
+                                           const int strip, const int y0, const int y1)
+{
+    using N = double;  // node-local arithmetic (moments, stencils, collision)
+    const int lane = threadIdx.x & (WAVE - 1);
+    int col = (strip * STRIP - HALO + lane) % Lx;
+    if (col < 0) col += Lx;
+    const bool out_lane = lane >= HALO && lane < WAVE - HALO && (strip * STRIP + lane - HALO) < Lx;
+    const int walls = C->walls;
+    // rows y0-2 .. y1+1 are read; the loop runs in groups of four (the ring
+    // period), and the few extra rows of the last group are computed, not stored
+    const int niter = (y1 - y0) + 4;
+    const int niter4 = (niter + 3) & ~3;
+
+    auto load_row = [&](int r, R (&v)[16]) {
+        if (walls && (r < 0 || r >= Ly)) {
+            const R* g = (r < 0) ? C->ghost_lo : C->ghost_hi;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = g[k];
+        } else {
+            int rr = r % Ly;
+            if (rr < 0) rr += Ly;
+            // uniform plane base + 32-bit byte offset (a plane is < 4 GiB)
+            const R* base = fin + (int64_t)rr * Lx + col;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = base[k * plane];
+        }
+    };
+
+    // Ring of four rows per velocity.  At phase P (= t mod 4) B[P] receives
+    // the new row r, and B[P+1], B[P+2], B[P+3] (mod 4) hold rows j-1, j, j+1
+    // of the output row j = r - 2; roles move by index, never by copying.
+    R B[4][16];
+    // carries per velocity: the upwind x-difference D1 of the row the CTU1
+    // part reuses, and for CTU2 Y' at row j and dX = X'_{i+1} - X'_i at row
+    // j-1 (s_y > 0) or j (s_y < 0)
+    R cD1[16], cY[16], cdX[16];
+    // per-row stencil rings (same indexing by phase): density deviation sums
+    // and their x-sums (row r), Laplacian rows and their x-differences and
+    // x-sums (row r-1), pending 24-neighbour gradient sums (rows r-2 .. r+1)
+    N dsr[4], hsr[4], Lr[4], dLr[4], sLr[4], ax[4], ay[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) B[i][k] = R(0);
+        dsr[i] = hsr[i] = Lr[i] = dLr[i] = sLr[i] = ax[i] = ay[i] = N(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cD1[k] = cY[k] = cdX[k] = R(0);
+
+    // the next row is loaded one row ahead (software pipelining)
+    R NX[16];
+    load_row(y0 - 2, NX);
+    auto body = [&](auto ph, const int t) {
+        constexpr int P = decltype(ph)::value;
+        constexpr int iN = P, iM1 = (P + 1) & 3, i0 = (P + 2) & 3, iP1 = (P + 3) & 3;
+        R(&cur)[16] = B[iN];
+        R(&fm1)[16] = B[iM1];
+        R(&f0)[16] = B[i0];
+        R(&fp1)[16] = B[iP1];
+        const int r = y0 - 2 + t;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cur[k] = NX[k];
+        load_row(r + 1, NX);
+        const bool ghost = walls && (r < 0 || r >= Ly);
+
+        // moments of the output row j = r - 2 (independent of the new row, so
+        // they overlap its loads): u = sum f xi / rho, a2 = sum f (xi xi - I)
+        // (w_k rho_ref drops out of both)
+        N jx = 0, jy = 0, axx = 0, axy = 0, ayy = 0;
+        static_for<0, 4>([&](auto gc) {
+            constexpr int G = decltype(gc)::value;
+            constexpr N qx = group_qx(G), qy = group_qy(G);
+            const N d0 = f0[4 * G], d1 = f0[4 * G + 1], d2 = f0[4 * G + 2], d3 = f0[4 * G + 3];
+            const N see = (d0 + d1) + (d2 + d3);
+            const N soe = (d0 - d1) - (d2 - d3);
+            const N seo = (d0 + d1) - (d2 + d3);
+            const N soo = (d0 - d1) + (d2 - d3);
+            jx += qx * soe;
+            jy += qy * seo;
+            axx += (qx * qx - 1.0) * see;
+            ayy += (qy * qy - 1.0) * see;
+            axy += (qx * qy) * soo;
+        });
+
+        // --- regularization of the new row (Eq. ereg): project onto the Hermite
+        // space of order <= 3.  Linear in f and exact on w_k rho_ref, so it
+        // acts on the stored deviations as they are.
+        if constexpr (REG) {
+            if (!ghost) {
+                N a[4][4];  // a[m][n] = sum_k d_k He_m(xi_x) He_n(xi_y), m + n <= 3
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) a[m][n] = N(0);
+                static_for<0, 4>([&](auto gc) {
+                    constexpr int G = decltype(gc)::value;
+                    constexpr N qx = group_qx(G), qy = group_qy(G);
+                    constexpr N hx[4] = {1.0, qx, qx * qx - 1.0, qx * qx * qx - 3.0 * qx};
+                    constexpr N hy[4] = {1.0, qy, qy * qy - 1.0, qy * qy * qy - 3.0 * qy};
+                    const N d0 = cur[4 * G], d1 = cur[4 * G + 1], d2 = cur[4 * G + 2], d3 = cur[4 * G + 3];
+                    const N see = (d0 + d1) + (d2 + d3);   // even in x, even in y
+                    const N soe = (d0 - d1) - (d2 - d3);   // odd in x
+                    const N seo = (d0 + d1) - (d2 + d3);   // odd in y
+                    const N soo = (d0 - d1) + (d2 - d3);   // odd in both
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+#pragma unroll
+                        for (int n = 0; n < 4 - m; ++n) {
+                            const N s = (m & 1) ? ((n & 1) ? soo : soe) : ((n & 1) ? seo : see);
+                            a[m][n] += hx[m] * hy[n] * s;
+                        }
+                });
+                // coefficients of the reconstruction w_k sum a_mn He_m He_n / (m! n!)
+                constexpr N fact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4 - m; ++n) a[m][n] *= fact[m] * fact[n];
+                static_for<0, 4>([&](auto gc) {
+                    constexpr int G = decltype(gc)::value;
+                    constexpr N qx = group_qx(G), qy = group_qy(G), w = group_w(G);
+                    constexpr N hx[4] = {1.0, qx, qx * qx - 1.0, qx * qx * qx - 3.0 * qx};
+                    constexpr N hy[4] = {1.0, qy, qy * qy - 1.0, qy * qy * qy - 3.0 * qy};
+                    const N EE = a[0][0] + a[2][0] * hx[2] + a[0][2] * hy[2];
+                    const N OE = a[1][0] * hx[1] + a[3][0] * hx[3] + a[1][2] * (hx[1] * hy[2]);
+                    const N EO = a[0][1] * hy[1] + a[0][3] * hy[3] + a[2][1] * (hx[2] * hy[1]);
+                    const N OO = a[1][1] * (hx[1] * hy[1]);
+                    const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
+                    cur[4 * G + 0] = (R)(w * (Pp + Sp));   // (+,+)
+                    cur[4 * G + 1] = (R)(w * (Pm - Sm));   // (-,+)
+                    cur[4 * G + 2] = (R)(w * (Pp - Sp));   // (-,-)
+                    cur[4 * G + 3] = (R)(w * (Pm + Sm));   // (+,-)
+                });
+            }
+        }
+
+        // --- density of the new row and the force stencils (Eq. eder) --------
+        N ds_r;
+        if (ghost) {
+            ds_r = ((r < 0) ? C->ghost_rho_lo : C->ghost_rho_hi) - C->rho0;
+        } else {
+            ds_r = (N)cur[0];
+#pragma unroll
+            for (int k = 1; k < 16; ++k) ds_r += (N)cur[k];
+        }
+        const N rho_r = C->rho0 + ds_r;
+        // p^i - p^w = rho T - rho T/(1 - b rho) + a rho^2 = rho^2 (a - b T/(1 - b rho))
+        const N phi_r = rho_r * rho_r * (C->a_vdw - C->b_vdw * C->T / (1.0 - C->b_vdw * rho_r));
+
+        // 9-point isotropic Laplacian of rho at row r-1 (rho0 drops out)
+        const N ds_m1 = dsr[iP1], ds_m2 = dsr[i0];
+        const N hs_r = from_left(ds_r) + from_right(ds_r);
+        const N L_m1 = (4.0 * (hsr[iP1] + ds_r + ds_m2) + hs_r + hsr[i0] - 20.0 * ds_m1) * C->inv_6ds2;
+        const N Lrr = from_right(L_m1), Lll = from_left(L_m1);
+        const N dL_m1 = Lrr - Lll, sL_m1 = Lrr + Lll;
+        // 9-point isotropic gradient of the Laplacian at row j = r-2
+        const N g3x = (1.0 / 3.0) * dLr[iP1] + (1.0 / 12.0) * (dL_m1 + dLr[i0]);
+        const N g3y = (1.0 / 3.0) * (L_m1 - Lr[i0]) + (1.0 / 12.0) * (sL_m1 - sLr[i0]);
+        dsr[iN] = ds_r;
+        hsr[iN] = hs_r;
+        Lr[iN] = L_m1;
+        dLr[iN] = dL_m1;
+        sLr[iN] = sL_m1;
+
+        // 24-neighbour isotropic gradient of p^i - p^w: row r adds to rows
+        // r-2 .. r+2; ax/ay[(P + d) mod 4] hold the sums of row r-2+d
+        N g5x, g5y;
+        {
+            using W = G5W<N>;
+            const N p1 = from_right(phi_r), m1 = from_left(phi_r);
+            const N p2 = from_right(p1), m2 = from_left(m1);
+            const N dx1 = p1 - m1, dx2 = p2 - m2, s1 = p1 + m1, s2 = p2 + m2;
+            const N A0 = W::w1 * dx1 + 2.0 * W::w4 * dx2;
+            const N A1 = W::w2 * dx1 + 2.0 * W::w5 * dx2;
+            const N A2 = W::w5 * dx1 + 2.0 * W::w8 * dx2;
+            const N B1 = W::w1 * phi_r + W::w2 * s1 + W::w5 * s2;
+            const N B2 = W::w4 * phi_r + W::w5 * s1 + W::w8 * s2;
+            g5x = ax[iN] + A2;
+            g5y = ay[iN] + 2.0 * B2;
+            ax[iM1] += A1;
+            ay[iM1] += B1;
+            ax[i0] += A0;
+            ax[iP1] += A1;
+            ay[iP1] -= B1;
+            ax[iN] = A2;
+            ay[iN] = -2.0 * B2;
+        }
+
+        // --- node quantities of the output row j = r - 2 ------------------------
+        const N ds_j = ds_m2;
+        const N rho_j = C->rho0 + ds_j;
+        const N inv_rho = 1.0 / rho_j;
+        const N gx = g5x * C->inv_ds * inv_rho + C->kappa_ds * g3x;
+        const N gy = g5y * C->inv_ds * inv_rho + C->kappa_ds * g3y;
+        const N ux = jx * inv_rho, uy = jy * inv_rho;
+
+        // collision + force as dt/tau f^eq_k + dt F_k = w_k sum_mn c_mn xi_x^m xi_y^n;
+        // in deviation storage c00 also absorbs -dt/tau rho_ref
+        N c00, c10, c01, c20, c02, c11, c30, c21, c12, c03;
+        {
+            const N dtt = C->dt_tau, dt = C->dt, T1 = C->Tm1;
+            const N hu = 0.5 * (ux * ux + uy * uy);
+            const N hT = 0.5 * T1;
+            const N tr = axx + ayy;
+            const N vx = axx * gx + axy * gy, vy = axy * gx + ayy * gy;
+            const N gu = gx * ux + gy * uy;
+            const N lin = 1.0 - hu - 2.0 * T1;
+            c00 = dtt * (ds_j - rho_j * (hu + T1)) - dt * rho_j * gu;
+            c10 = dtt * rho_j * ux * lin + dt * (rho_j * gx - 0.5 * gx * tr - vx);
+            c01 = dtt * rho_j * uy * lin + dt * (rho_j * gy - 0.5 * gy * tr - vy);
+            c20 = dtt * rho_j * (0.5 * ux * ux + hT) + dt * rho_j * gx * ux;
+            c02 = dtt * rho_j * (0.5 * uy * uy + hT) + dt * rho_j * gy * uy;
+            c11 = dtt * rho_j * ux * uy + dt * rho_j * (gx * uy + gy * ux);
+            c30 = dtt * rho_j * ux * (ux * ux * (1.0 / 6.0) + hT) + dt * 0.5 * gx * axx;
+            c21 = dtt * rho_j * uy * (0.5 * ux * ux + hT) + dt * (gx * axy + 0.5 * gy * axx);
+            c12 = dtt * rho_j * ux * (0.5 * uy * uy + hT) + dt * (0.5 * gx * ayy + gy * axy);
+            c03 = dtt * rho_j * uy * (uy * uy * (1.0 / 6.0) + hT) + dt * 0.5 * gy * ayy;
+        }
+
+        const bool store_row = t >= 4 && r - 2 < y1;
+        R* const orow = fout + (int64_t)(r - 2) * Lx + col;
+        const N dtt = C->dt_tau;
+
+        // collision + force increment w_k P_k - dt/tau d_k of velocity 4G+s,
+        // from the even/odd parts of the polynomial of group G (formed in FP64)
+        auto group_poly = [&](auto gc, N(&poly)[4]) {
+            constexpr int G = decltype(gc)::value;
+            constexpr N qx = group_qx(G), qy = group_qy(G), wg = group_w(G);
+            const N EE = c00 + c20 * (qx * qx) + c02 * (qy * qy);
+            const N OE = qx * (c10 + c30 * (qx * qx) + c12 * (qy * qy));
+            const N EO = qy * (c01 + c03 * (qy * qy) + c21 * (qx * qx));
+            const N OO = (qx * qy) * c11;
+            const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
+            poly[0] = wg * (Pp + Sp) - dtt * (N)f0[4 * G + 0];
+            poly[1] = wg * (Pm - Sm) - dtt * (N)f0[4 * G + 1];
+            poly[2] = wg * (Pp - Sp) - dtt * (N)f0[4 * G + 2];
+            poly[3] = wg * (Pm + Sm) - dtt * (N)f0[4 * G + 3];
+        };
+        // with FP32 storage the 16 increments are rounded to FP32 up front, so
+        // the FP64 coefficients are not held through the advection below
+        constexpr bool EARLY = std::is_same<R, float>::value;
+        R coll_all[16];
+        if constexpr (EARLY) {
+            static_for<0, 4>([&](auto gc) {
+                constexpr int G = decltype(gc)::value;
+                N poly[4];
+                group_poly(gc, poly);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) coll_all[4 * G + s] = (R)poly[s];
+            });
+        }
+
+        static_for<0, 4>([&](auto gc) {
+            constexpr int G = decltype(gc)::value;
+            N poly[4];
+            if constexpr (!EARLY) group_poly(gc, poly);
+
+            static_for<0, 4>([&](auto sc) {
+                constexpr int K = 4 * G + decltype(sc)::value;
+                constexpr int SX = sign_x(K), SY = sign_y(K), MX = mag_x(K), MY = mag_y(K);
+                const R fj = f0[K];
+                // advective increment A_k(f) - f from upwind differences (exact on
+                // constants): with D1 = f(i - s_x) - f(i) on the output row and on
+                // the row upwind in y, D2 = f(j - s_y) - f(j), the CTU1 part is
+                // a D1 + b D2 + a b (D1(j - s_y) - D1(j)).  D1 of the row that is
+                // reused one row later is carried in cD1.
+                R inc;
+                if constexpr (SY > 0) {
+                    const R rx = fj - from_left(fj);          // R^x at row j
+                    const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
+                    const R D1 = (SX > 0) ? -rx : rxu;
+                    const R D2 = fm1[K] - fj;
+                    inc = C->a[MX] * D1 + C->a[MY] * D2 + C->ab[MX][MY] * (cD1[K] - D1);
+                    cD1[K] = D1;
+                    if constexpr (SCHEME == 2) {
+                        // X' at row j and its x-difference; dX of row j-1 is carried
+                        const R X = mc_half(rx, rxu);
+                        const R dXj = from_right(X) - X;
+                        // Y' at row j+1 (ratio with R^y of row j = -D2); Y' of row j is carried
+                        const R Y1 = mc_half(fp1[K] - fj, -D2);
+                        const R dY = Y1 - cY[K];
+                        inc += C->xs1[MX][MY] * dXj + C->xs2[MX][MY] * cdX[K] + C->ys1[MX][MY] * dY
+                             + C->ys2[MX][MY] * upwind_x<SX>(dY);
+                        cdX[K] = dXj;
+                        cY[K] = Y1;
+                    }
+                } else {
+                    const R fjp = fp1[K];
+                    const R rx = fjp - from_left(fjp);        // R^x at row j+1
+                    const R rxu = upwind_x<SX>(rx);
+                    const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row j+1
+                    const R D2 = fjp - fj;
+                    inc = C->a[MX] * cD1[K] + C->a[MY] * D2 + C->ab[MX][MY] * (D1p - cD1[K]);
+                    cD1[K] = D1p;
+                    if constexpr (SCHEME == 2) {
+                        // X' at row j+1 and its x-difference; dX of row j is carried
+                        const R X = mc_half(rx, rxu);
+                        const R dXjp = from_right(X) - X;
+                        // Y' at row j+1 (ratio with R^y of row j+2); Y' of row j is carried
+                        const R Y1 = mc_half(D2, cur[K] - fjp);
+                        const R dY = Y1 - cY[K];
+                        inc += C->xs1[MX][MY] * cdX[K] + C->xs2[MX][MY] * dXjp + C->ys1[MX][MY] * dY
+                             + C->ys2[MX][MY] * upwind_x<SX>(dY);
+                        cdX[K] = dXjp;
+                        cY[K] = Y1;
+                    }
+                }
+                R coll;
+                if constexpr (EARLY) coll = coll_all[K];
+                else coll = (R)poly[decltype(sc)::value];
+                const R fnew = fj + (inc + coll);
+                if (store_row && out_lane)
+                    orow[K * plane] = fnew;
+            });
+        });
+    };
+
+    // scheduling barriers keep the compiler from interleaving consecutive row
+    // bodies (which would raise register pressure past two wavefronts per SIMD)
+    for (int t = 0; t < niter4; t += 4) {
+        body(std::integral_constant<int, 0>{}, t);
+        __builtin_amdgcn_sched_barrier(0);
+        body(std::integral_constant<int, 1>{}, t + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        body(std::integral_constant<int, 2>{}, t + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        body(std::integral_constant<int, 3>{}, t + 3);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Wavefront id -> workgroup order that keeps neighbouring strips on one XCD:
+// workgroups are dealt round-robin to the 8 XCDs, so workgroup b runs on XCD
+// b % 8; remap so that each XCD gets one contiguous range of logical ids.
+__device__ __forceinline__ int xcd_logical_block(int b, int nblocks)
+{
+    constexpr int NXCD = 8;
+    const int q = nblocks / NXCD, rem = nblocks % NXCD;
+    const int x = b % NXCD, i = b / NXCD;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
+// One wavefront per SIMD with the full register file (up to 512 registers,
+// no spills to memory); the next row is prefetched to cover load latency.
+template <typename R> struct WavesPerEU { static constexpr int value = 1; };
+
+template <typename R, int SCHEME, bool REG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::value))) void step_kernel(const R* __restrict__ fin, R* __restrict__ fout,
+                                                   const StepCoef<R>* __restrict__ coef,
+                                                   int Lx, int Ly, int64_t plane, int rows,
+                                                   int nstrips, int nwaves)
+{
+    const int wpg = blockDim.x / WAVE;
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    // the wavefront index is the same in all 64 lanes: keep it scalar
+    const int wave = __builtin_amdgcn_readfirstlane(lb * wpg + (int)(threadIdx.x / WAVE));
+    if (wave >= nwaves) return;  // whole wavefront leaves together
+    const int chunk = wave / nstrips, strip = wave - chunk * nstrips;
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, Ly);
+    strip_step<R, SCHEME, REG>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1);
+}
+
+template <typename R, int SCHEME, bool REG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::value))) void batch_step_kernel(const BatchRun<R>* __restrict__ runs,
+                                                         const StepCoef<R>* __restrict__ coefs,
+                                                         const BatchItem* __restrict__ items,
+                                                         int nitems, int cur)
+{
+    const int wpg = blockDim.x / WAVE;
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int w = __builtin_amdgcn_readfirstlane(lb * wpg + (int)(threadIdx.x / WAVE));
+    if (w >= nitems) return;
+    const BatchItem it = items[w];
+    const BatchRun<R> run = runs[it.run];
+    const int y0 = it.chunk * run.rows;
+    const int y1 = min(y0 + run.rows, run.Ly);
+    strip_step<R, SCHEME, REG>(run.f[cur], run.f[cur ^ 1], coefs + it.run,
+                                                              run.Lx, run.Ly, run.plane, it.strip, y0, y1);
+}
+
+// ----------------------------------------------------------------------------
+// auxiliary kernels (all in FP64 arithmetic)
+
+__device__ __forceinline__ double feq_k(int k, double T, double rho, double ux, double uy)
+{
+    // Eq. (herfeq)
+    const double cx = xi_x(k), cy = xi_y(k);
+    const double xu = cx * ux + cy * uy, u2 = ux * ux + uy * uy, x2 = cx * cx + cy * cy;
+    return weight(k) * rho
+         * (1.0 + xu + 0.5 * (xu * xu - u2 + (T - 1.0) * (x2 - 2.0))
+            + xu * (1.0 / 6.0) * (xu * xu - 3.0 * u2 + 3.0 * (T - 1.0) * (x2 - 4.0)));
+}
+
+template <typename R>
+__global__ void init_kernel(R* __restrict__ f, const StepCoef<R>* __restrict__ C, const double* __restrict__ rho,
+                            const double* __restrict__ ux, const double* __restrict__ uy, int64_t n)
+{
+    const double T = (double)C->T;
+    const double rho0 = (double)C->rho0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double r = rho[i], vx = ux[i], vy = uy[i];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) f[k * n + i] = (R)(feq_k(k, T, r, vx, vy) - weight(k) * rho0);
+    }
+}
+
+template <typename R>
+__global__ void moments_kernel(const R* __restrict__ f, const StepCoef<R>* __restrict__ C, double* __restrict__ rho,
+                               double* __restrict__ ux, double* __restrict__ uy, int64_t n)
+{
+    const double rho0 = (double)C->rho0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double r = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const double v = (double)f[k * n + i] + weight(k) * rho0;
+            r += v;
+            jx += v * xi_x(k);
+            jy += v * xi_y(k);
+        }
+        rho[i] = r;
+        ux[i] = jx / r;
+        uy[i] = jy / r;
+    }
+}
+
+template <typename R>
+__global__ void get_plane_kernel(const R* __restrict__ f, const StepCoef<R>* __restrict__ C, int k,
+                                 double* __restrict__ out, int64_t n)
+{
+    const double off = weight(k) * (double)C->rho0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (double)f[k * n + i] + off;
+}
+
+template <typename R>
+__global__ void set_plane_kernel(R* __restrict__ f, const StepCoef<R>* __restrict__ C, int k,
+                                 const double* __restrict__ in, int64_t n)
+{
+    const double off = weight(k) * (double)C->rho0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        f[k * n + i] = (R)(in[i] - off);
+}
+
+// FP64 sums over the lattice: mass, momentum, bubble count, non-finite count
+// and the first and second position moments of the bubble (rho < threshold).
+template <typename R>
+__global__ __launch_bounds__(256) void reduce_kernel(const R* __restrict__ f, const StepCoef<R>* __restrict__ C,
+                                                     int Lx, int Ly, double threshold,
+                                                     double* __restrict__ partials)
+{
+    const int64_t n = (int64_t)Lx * Ly;
+    const double rho0 = (double)C->rho0;
+    const double cxn = 0.5 * (Lx - 1), cyn = 0.5 * (Ly - 1);
+    double acc[REDUCE_VALUES];
+#pragma unroll
+    for (int v = 0; v < REDUCE_VALUES; ++v) acc[v] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double r = 0.0, jx = 0.0, jy = 0.0;
+        bool finite = true;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const double v = (double)f[k * n + i] + weight(k) * rho0;
+            finite = finite && isfinite(v);
+            r += v;
+            jx += v * xi_x(k);
+            jy += v * xi_y(k);
+        }
+        acc[0] += r;
+        acc[1] += jx;
+        acc[2] += jy;
+        if (!finite) acc[4] += 1.0;
+        if (r < threshold) {
+            const int64_t jj = i / Lx;
+            const double x = (double)(i - jj * Lx) - cxn, y = (double)jj - cyn;
+            acc[3] += 1.0;
+            acc[5] += x;
+            acc[6] += y;
+            acc[7] += x * x;
+            acc[8] += x * y;
+            acc[9] += y * y;
+        }
+    }
+    // wavefront reduction, then across the workgroup's wavefronts in LDS
+    __shared__ double lds[256 / WAVE][REDUCE_VALUES];
+#pragma unroll
+    for (int v = 0; v < REDUCE_VALUES; ++v) {
+        double s = acc[v];
+#pragma unroll
+        for (int off = WAVE / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+        acc[v] = s;
+    }
+    const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
+    if (ln == 0) {
+#pragma unroll
+        for (int v = 0; v < REDUCE_VALUES; ++v) lds[wv][v] = acc[v];
+    }
+    __syncthreads();
+    if (threadIdx.x < REDUCE_VALUES) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) s += lds[w][threadIdx.x];
+        partials[blockIdx.x * REDUCE_VALUES + threadIdx.x] = s;
+    }
+}
+
+// Sum of the block partials in a fixed order (deterministic).
+__global__ __launch_bounds__(64) void reduce_final_kernel(const double* __restrict__ partials, int nblocks,
+                                                          double* __restrict__ out)
+{
+    const int v = threadIdx.x;
+    if (v < REDUCE_VALUES) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += partials[b * REDUCE_VALUES + v];
+        out[v] = s;
+    }
+}
+
+int grid_for(int64_t n, int block)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// launchers
+
+template <typename R>
+hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int wpg, hipStream_t s)
+{
+    const int nchunks = (rv.Ly + rv.rows - 1) / rv.rows;
+    const int nwaves = rv.nstrips * nchunks;
+    const int nblocks = (nwaves + wpg - 1) / wpg;
+    const dim3 grid(nblocks), block(WAVE * wpg);
+#define LBM_LAUNCH(SC, RG)                                                                              \
+    hipLaunchKernelGGL((step_kernel<R, SC, RG>), grid, block, 0, s, rv.f_in, rv.f_out, rv.coef, rv.Lx, \
+                       rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
+    if (scheme == 1) {
+        if (regularize) LBM_LAUNCH(1, true);
+        else LBM_LAUNCH(1, false);
+    } else {
+        if (regularize) LBM_LAUNCH(2, true);
+        else LBM_LAUNCH(2, false);
+    }
+#undef LBM_LAUNCH
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coefs, const BatchItem* d_items,
+                             int32_t nitems, int32_t cur, int scheme, int regularize, int wpg, hipStream_t s)
+{
+    const int nblocks = (nitems + wpg - 1) / wpg;
+    const dim3 grid(nblocks), block(WAVE * wpg);
+#define LBM_LAUNCH(SC, RG) \
+    hipLaunchKernelGGL((batch_step_kernel<R, SC, RG>), grid, block, 0, s, d_runs, d_coefs, d_items, nitems, cur)
+    if (scheme == 1) {
+        if (regularize) LBM_LAUNCH(1, true);
+        else LBM_LAUNCH(1, false);
+    } else {
+        if (regularize) LBM_LAUNCH(2, true);
+        else LBM_LAUNCH(2, false);
+    }
+#undef LBM_LAUNCH
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_init(R* f, const StepCoef<R>* coef, const double* rho, const double* ux, const double* uy,
+                       int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((init_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, rho, ux, uy, n);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_moments(const R* f, const StepCoef<R>* coef, double* rho, double* ux, double* uy, int64_t n,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL((moments_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, rho, ux, uy, n);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_get_plane(const R* f, const StepCoef<R>* coef, int k, double* out, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((get_plane_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, k, out, n);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_set_plane(R* f, const StepCoef<R>* coef, int k, const double* in, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((set_plane_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, k, in, n);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_t Ly, double threshold,
+                         double* partials, int32_t max_blocks, double* result, hipStream_t s)
+{
+    int nb = grid_for((int64_t)Lx * Ly, 256);
+    if (nb > max_blocks) nb = max_blocks;
+    hipLaunchKernelGGL((reduce_kernel<R>), dim3(nb), dim3(256), 0, s, f, coef, Lx, Ly, threshold, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+#define LBM_INSTANTIATE(R)                                                                                   \
+    template hipError_t launch_step<R>(const RunView<R>&, int, int, int, hipStream_t);                       \
+    template hipError_t launch_batch_step<R>(const BatchRun<R>*, const StepCoef<R>*, const BatchItem*,       \
+                                             int32_t, int32_t, int, int, int, hipStream_t);                  \
+    template hipError_t launch_init<R>(R*, const StepCoef<R>*, const double*, const double*, const double*, \
+                                       int64_t, hipStream_t);                                                \
+    template hipError_t launch_moments<R>(const R*, const StepCoef<R>*, double*, double*, double*, int64_t, \
+                                          hipStream_t);                                                      \
+    template hipError_t launch_get_plane<R>(const R*, const StepCoef<R>*, int, double*, int64_t, hipStream_t); \
+    template hipError_t launch_set_plane<R>(R*, const StepCoef<R>*, int, const double*, int64_t, hipStream_t); \
+    template hipError_t launch_reduce<R>(const R*, const StepCoef<R>*, int32_t, int32_t, double, double*,    \
+                                         int32_t, double*, hipStream_t);
+LBM_INSTANTIATE(float)
+LBM_INSTANTIATE(double)
+#undef LBM_INSTANTIATE
+
+}  // namespace lbm

@@ -1,0 +1,309 @@
+"""Parity of the HIP stepper (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances, derived from the arithmetic (every kernel sums in a different
+order than the oracle and contracts multiply-adds):
+  * FP64 storage: one step agrees to a few units in the last place of the
+    largest f (bound 1e-13 relative); after many steps rounding differences
+    stay below 1e-10 relative in rho and u.
+  * FP32 deviation storage: the stored f_k - w_k rho_ref carries a relative
+    rounding of 6e-8, so one step agrees to 1e-6 of max|f|; rho and u after
+    many steps follow the 1e-5 bar (u normalised by its largest value).
+"""
+import numpy as np
+import pytest
+
+import oracle as o
+from gpu_helpers import field_errors, oracle_params, random_state, rel_err
+from paper_1802_01272_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_1802_01272_amd.lbm")
+
+F64_STEP = 1e-13
+F32_STEP = 2e-6
+
+
+def make_params(Lx, Ly, scheme=2, reg=0, bc=0, precision=0, **kw):
+    p = lbm.Params(Lx=Lx, Ly=Ly, T=0.93, kappa=0.8, tau=0.7, scheme=scheme, regularize=reg, bc_y=bc,
+                   u_wall=0.04 if bc else 0.0, rho_wall=1.25, precision=precision, rho_ref=1.2)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def gpu_step_from(p, f, nsteps=1, launch=None):
+    run = lbm.Run(p, 1.0, 0.0, 0.0)
+    if launch:
+        run.set_launch(*launch)
+    run.set_f(f)
+    run.step(nsteps)
+    out = run.get_f()
+    run.close()
+    return out
+
+
+# ---------------------------------------------------------------- init / I-O
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_init_is_equilibrium(precision):
+    p = make_params(37, 23, precision=precision)
+    rng = np.random.default_rng(1)
+    rho = 1.1 + 0.3 * rng.random((23, 37))
+    ux, uy = 0.05 * rng.standard_normal((2, 23, 37))
+    run = lbm.Run(p, rho, ux, uy)
+    f = run.get_f()
+    ref = o.init(oracle_params(p), rho, ux, uy)
+    assert rel_err(f, ref) < (1e-15 if precision == 0 else 1e-7)
+    r, vx, vy = run.moments()
+    tol = 1e-14 if precision == 0 else 2e-7
+    np.testing.assert_allclose(r, rho, rtol=tol)
+    np.testing.assert_allclose(vx, ux, atol=tol)
+    np.testing.assert_allclose(vy, uy, atol=tol)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_set_get_roundtrip(precision):
+    p = make_params(70, 11, precision=precision)
+    f = random_state(p, 2)
+    run = lbm.Run(p, 1.0, 0.0, 0.0)
+    run.set_f(f)
+    g = run.get_f()
+    if precision == 0:
+        assert np.array_equal(f, g)
+    else:
+        assert rel_err(g, f) < 1e-7
+
+
+# ------------------------------------------------------------ one-step parity
+
+SIZES = [(16, 16), (64, 64), (96, 64), (61, 37), (130, 9)]
+
+
+@pytest.mark.parametrize("Lx,Ly", SIZES)
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("reg", [0, 1])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_one_step_fp64(Lx, Ly, scheme, reg, bc):
+    p = make_params(Lx, Ly, scheme, reg, bc)
+    f = random_state(p, 10 + Lx + 3 * Ly + scheme)
+    got = gpu_step_from(p, f)
+    ref = o.step(oracle_params(p), f)
+    assert rel_err(got, ref) < F64_STEP
+
+
+@pytest.mark.parametrize("Lx,Ly", [(64, 64), (61, 37)])
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("reg", [0, 1])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_one_step_fp32dev(Lx, Ly, scheme, reg, bc):
+    p = make_params(Lx, Ly, scheme, reg, bc, precision=1)
+    f = random_state(p, 20 + Lx + scheme)
+    got = gpu_step_from(p, f)
+    # the oracle steps the same FP32-rounded state the GPU holds
+    run = lbm.Run(p, 1.0, 0.0, 0.0)
+    run.set_f(f)
+    f_stored = run.get_f()
+    ref = o.step(oracle_params(p), f_stored)
+    assert rel_err(got, ref) < F32_STEP
+
+
+@pytest.mark.parametrize("Lx,Ly", [(1, 1), (1, 6), (2, 3), (5, 1), (59, 4), (60, 2), (63, 5), (64, 3), (65, 7),
+                                   (121, 2), (200, 1)])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_one_step_edge_sizes(Lx, Ly, bc):
+    """Lattices narrower than a wavefront, ragged last strips, a single row or column."""
+    p = make_params(Lx, Ly, 2, 0, bc)
+    f = random_state(p, 30 + Lx + Ly)
+    got = gpu_step_from(p, f)
+    ref = o.step(oracle_params(p), f)
+    assert rel_err(got, ref) < F64_STEP
+
+
+@pytest.mark.parametrize("launch", [(1, 1), (3, 2), (7, 4), (64, 1), (256, 2)])
+def test_launch_shape_does_not_change_results(launch):
+    p = make_params(130, 45, 2, 1, 1)
+    f = random_state(p, 40)
+    base = gpu_step_from(p, f, nsteps=3, launch=(16, 2))
+    got = gpu_step_from(p, f, nsteps=3, launch=launch)
+    assert np.array_equal(base, got)
+
+
+# ------------------------------------------------------------ many steps
+
+def test_flat_interface_small_config_fp64_parity():
+    """64 x 64 flat interface (a = 9/49, b = 2/21, T = 0.9 T_c, tau = 0.8,
+    CTU2, dt = ds/4), 1000 steps: FP64 GPU against the oracle."""
+    w = I.flat_interface_small()
+    p = lbm.Params.from_workload(w)
+    rho, ux, uy = w.fields()
+    run = lbm.Run(p, rho, ux, uy)
+    run.step(w.steps)
+    r, vx, vy = run.moments()
+    op = oracle_params(p)
+    f = o.run(op, o.init(op, rho, ux, uy), w.steps)
+    rr, rx, ry = o.field_moments(op, f)
+    e = field_errors(r, vx, vy, rr, rx, ry)
+    print("flat interface 64^2, 1000 steps, FP64 GPU vs oracle:", e)
+    assert e["rho_max"] < 1e-10 and e["u_max"] < 1e-9
+
+
+def test_bubble_fp32dev_against_oracle():
+    """Quiescent bubble (T = 0.95, rho_ext = 0.95 rho_L, R = 12) on 96 x 96 for
+    600 steps: FP32 deviation storage against the FP64 oracle."""
+    w = I.quiescent_bubble(96, radius=12.0)
+    rho, ux, uy = w.fields()
+    p = lbm.Params.from_workload(w, precision=lbm.FP32_DEV)
+    run = lbm.Run(p, rho, ux, uy)
+    run.step(600)
+    r, vx, vy = run.moments()
+    op = oracle_params(p)
+    f = o.run(op, o.init(op, rho, ux, uy), 600)
+    rr, rx, ry = o.field_moments(op, f)
+    e = field_errors(r, vx, vy, rr, rx, ry)
+    print("bubble 96^2, 600 steps, FP32-dev GPU vs oracle:", e)
+    assert e["rho_max"] < 1e-5 and e["u_max"] < 1e-4
+
+
+def test_sheared_bubble_regularized_fp64():
+    p = lbm.Params(Lx=80, Ly=72, T=0.95, kappa=1.0, tau=0.7, regularize=1, bc_y=1, u_wall=0.02,
+                   rho_wall=1.3886)
+    rho = I.bubble(80, 72, 0.579, 1.3886, 10.0)
+    ux, uy = I.shear_profile(80, 72, 2 * 0.02 / 72)
+    run = lbm.Run(p, rho, ux, uy)
+    run.step(300)
+    got = run.get_f()
+    op = oracle_params(p)
+    ref = o.run(op, o.init(op, rho, ux, uy), 300)
+    assert rel_err(got, ref) < 1e-10
+
+
+# ------------------------------------------------------------ diagnostics
+
+def test_reduce_matches_oracle_fp64():
+    w = I.quiescent_bubble(150, radius=25.0)
+    rho, ux, uy = w.fields()
+    p = lbm.Params.from_workload(w)
+    p.Lx, p.Ly = 150, 150
+    run = lbm.Run(p, rho, ux, uy)
+    run.step(5)
+    f = run.get_f()
+    thr = 0.5 * (w.rho_vapour + w.rho_liquid)
+    st = run.reduce(thr)
+    ref = o.reduce(oracle_params(p), f, thr)
+    assert st["n_bubble"] == int(ref["n_bubble"]) and st["n_nonfinite"] == 0
+    for k in ("mass", "sx", "sy", "sxx", "sxy", "syy"):
+        assert st[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-9), k
+    for k in ("mom_x", "mom_y"):
+        assert st[k] == pytest.approx(ref[k], abs=1e-10 * ref["mass"]), k
+    assert st["A_rel"] == pytest.approx(ref["n_bubble"] / 150 ** 2)
+    assert st["R_eq"] == pytest.approx(np.sqrt(ref["n_bubble"] / np.pi))
+
+
+def test_reduce_ellipse_shape():
+    """Gyration tensor of a synthetic elliptical bubble (semi-axes 40, 20,
+    tilted 0.3 rad): a, b, D and theta to within lattice discretisation."""
+    L = 200
+    A, B, th = 40.0, 20.0, 0.3
+    y, x = np.mgrid[0:L, 0:L].astype(float)
+    x -= (L - 1) / 2
+    y -= (L - 1) / 2
+    xr = x * np.cos(th) + y * np.sin(th)
+    yr = -x * np.sin(th) + y * np.cos(th)
+    inside = (xr / A) ** 2 + (yr / B) ** 2 < 1
+    rho = np.where(inside, 0.6, 1.4)
+    p = lbm.Params(Lx=L, Ly=L)
+    run = lbm.Run(p, rho, 0.0, 0.0)
+    st = run.reduce(1.0)
+    assert st["a"] == pytest.approx(A, rel=0.01)
+    assert st["b"] == pytest.approx(B, rel=0.02)
+    assert st["D"] == pytest.approx((A - B) / (A + B), abs=0.01)
+    assert st["theta"] == pytest.approx(th, abs=0.01)
+    assert st["cx"] == pytest.approx((L - 1) / 2, abs=0.05)
+
+
+def test_reduce_reports_nonfinite():
+    p = make_params(40, 30)
+    f = random_state(p, 50)
+    f[3, 7, 11] = np.nan
+    f[9, 0, 0] = np.inf
+    run = lbm.Run(p, 1.0, 0.0, 0.0)
+    run.set_f(f)
+    with pytest.raises(lbm.LbmError) as ei:
+        run.reduce(1.0)
+    assert ei.value.status == lbm.LBM_ENONFINITE
+    st = run.reduce(1.0, allow_nonfinite=True)
+    assert st["n_nonfinite"] == 2
+
+
+# ------------------------------------------------------------ determinism, resume, batch
+
+def test_bitwise_determinism():
+    p = make_params(128, 96, 2, 0, 1, precision=1)
+    f = random_state(p, 60)
+    a = gpu_step_from(p, f, nsteps=20)
+    b = gpu_step_from(p, f, nsteps=20)
+    assert np.array_equal(a, b)
+
+
+def test_checkpoint_resume_bitwise():
+    import torch
+    p = make_params(100, 64, 2, 0, 0)
+    f = random_state(p, 70)
+    run = lbm.Run(p, 1.0, 0.0, 0.0)
+    run.set_f(f)
+    run.step(9)
+    ws_copy = run.ws.clone()
+    torch.cuda.synchronize()
+    run.step(11)
+    end = run.get_f()
+    resumed = lbm.Run.attach(p, ws_copy, 9)
+    assert resumed.step_count == 9
+    resumed.step(11)
+    assert np.array_equal(resumed.get_f(), end)
+
+
+@pytest.mark.parametrize("graph_steps", [0, 4])
+def test_batch_equals_single_runs(graph_steps):
+    specs = [make_params(70, 50, bc=1), make_params(33, 19), make_params(128, 64, bc=1, T=0.9)]
+    states = [random_state(p, 80 + i) for i, p in enumerate(specs)]
+    singles = [gpu_step_from(p, f, nsteps=9) for p, f in zip(specs, states)]
+    batch = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
+    for m, f in zip(batch.runs, states):
+        m.set_f(f)
+    batch.step(5, graph_steps=graph_steps)
+    batch.step(4, graph_steps=graph_steps)
+    for m, ref in zip(batch.runs, singles):
+        assert m.step_count == 9
+        assert np.array_equal(m.get_f(), ref)
+
+
+def test_rejects_bad_parameters():
+    p = make_params(16, 16)
+    p.dt = 0.5
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Run(p, 1.0, 0.0, 0.0)
+    assert ei.value.status == lbm.LBM_ECFL
+    p = make_params(16, 16)
+    with pytest.raises(lbm.LbmError):
+        lbm.Run(p, np.full((16, 16), 4.0), 0.0, 0.0)  # beyond 1/b
+    with pytest.raises(lbm.LbmError):
+        lbm.Run(p, np.full((16, 16), np.nan), 0.0, 0.0)
+
+
+def test_fp32dev_ten_thousand_steps_against_oracle():
+    """The FP32-deviation bar: rho and u within 1e-5 of the FP64 oracle after
+    10^4 steps (quiescent bubble, T = 0.95, rho_ext = 0.95 rho_L, R = 14,
+    96 x 96 periodic, CTU2)."""
+    w = I.quiescent_bubble(96, radius=14.0)
+    rho, ux, uy = w.fields()
+    p = lbm.Params.from_workload(w, precision=lbm.FP32_DEV)
+    run = lbm.Run(p, rho, ux, uy)
+    run.step(10000)
+    r, vx, vy = run.moments()
+    op = oracle_params(p)
+    f = o.run(op, o.init(op, rho, ux, uy), 10000)
+    rr, rx, ry = o.field_moments(op, f)
+    e = field_errors(r, vx, vy, rr, rx, ry)
+    print("bubble 96^2, 10^4 steps, FP32-dev GPU vs oracle:", e)
+    assert e["rho_max"] < 1e-5 and e["u_max"] < 1e-5
