@@ -83,6 +83,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
+    ap.add_argument("--launch", default=None,
+                    help="fixed launch shape ROWS,WAVES (rows per wavefront, wavefronts per workgroup) instead of "
+                         "the autotuner's")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the lattice is advanced on a single device; "
@@ -95,6 +100,15 @@ def main():
     from paper_1802_01272_amd import lbm
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src_t = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst_t = torch.empty_like(src_t)
+        for _ in range(5):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 5 copies of %d bytes" % (src_t.numel() * 4), file=sys.stderr, flush=True)
+        del src_t, dst_t
+    fixed = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     w = I.large_lattice(args.L)
     rho, ux, uy = w.fields()
     nodes = w.Lx * w.Ly
@@ -104,7 +118,7 @@ def main():
         if name == "f64" and args.fp32_only:
             continue
         p = lbm.Params.from_workload(w, precision=prec)
-        launch = None if args.no_autotune else lbm.autotune(p, steps_per_trial=3)
+        launch = fixed if fixed else (None if args.no_autotune else lbm.autotune(p, steps_per_trial=3))
         run = lbm.Run(p, rho, ux, uy)
         if launch:
             run.set_launch(*launch)

@@ -60,7 +60,8 @@ enum { LBM_PERIODIC = 0, LBM_SHEAR_WALLS = 1 }; /* boundary in y                
 
 /* Parameters of one run.  Names follow the paper (Sec. II and III). */
 typedef struct {
-    int32_t Lx, Ly;       /* lattice nodes along x and y, each >= 1             */
+    int32_t Lx, Ly;       /* lattice nodes along x and y, each >= 1, and
+                             Lx * Ly <= 2^26 (8192 x 8192)                     */
     double ds, dt;        /* lattice spacing and time step; CFL of Sec. II C 1:
                              dt * sqrt(3 + sqrt 6) <= ds                       */
     double tau;           /* BGK relaxation time, > 0 (Eq. eBGK)                */

@@ -59,9 +59,9 @@ lbm_status validate(const lbm_params* p)
 {
     if (!p) return fail(LBM_EINVAL, "null parameters");
     if (p->Lx < 1 || p->Ly < 1) return fail(LBM_EINVAL, "Lx and Ly must be >= 1");
-    // one distribution plane must stay below 4 GiB (32-bit byte offsets)
-    if ((int64_t)p->Lx * (int64_t)p->Ly > (int64_t)1 << 29)
-        return fail(LBM_EINVAL, "Lx * Ly must not exceed 2^29 nodes");
+    // eight FP64 distribution planes must fit in 4 GiB (32-bit buffer offsets)
+    if ((int64_t)p->Lx * (int64_t)p->Ly > (int64_t)1 << 26)
+        return fail(LBM_EINVAL, "Lx * Ly must not exceed 2^26 nodes (8192 x 8192)");
     const double vals[] = {p->ds, p->dt, p->tau, p->T, p->a, p->b, p->kappa, p->rho_ref, p->u_wall, p->rho_wall};
     for (double v : vals)
         if (!is_finite_d(v)) return fail(LBM_EINVAL, "parameters must be finite");
@@ -179,6 +179,7 @@ struct lbm_batch {
     void* d_coefs = nullptr;  // StepCoef<R>[n]
     BatchItem* d_items = nullptr;
     int32_t nitems = 0;
+    int32_t nitems_periodic = 0;  // items [0, nitems_periodic) belong to periodic runs
     int cur = 0;
     int64_t step = 0;
     hipGraph_t graph = nullptr;
@@ -250,9 +251,9 @@ lbm_status step_once(lbm_run* r, hipStream_t s)
 {
     hipError_t e;
     if (r->p.precision == LBM_FP32_DEV)
-        e = launch_step<float>(view<float>(r), r->p.scheme, r->p.regularize, r->launch.waves_per_group, s);
+        e = launch_step<float>(view<float>(r), r->p.scheme, r->p.regularize, r->p.bc_y, r->launch.waves_per_group, s);
     else
-        e = launch_step<double>(view<double>(r), r->p.scheme, r->p.regularize, r->launch.waves_per_group, s);
+        e = launch_step<double>(view<double>(r), r->p.scheme, r->p.regularize, r->p.bc_y, r->launch.waves_per_group, s);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     r->cur ^= 1;
     r->step += 1;
@@ -674,7 +675,7 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
 {
     std::vector<BatchRun<R>> runs(b->n);
     std::vector<StepCoef<R>> coefs(b->n);
-    std::vector<BatchItem> items;
+    std::vector<BatchItem> items, wall_items;
     for (int i = 0; i < b->n; ++i) {
         lbm_run& r = b->runs[i];
         BatchRun<R>& br = runs[i];
@@ -688,9 +689,12 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
         br.plane = nodes(&r);
         fill_coef<R>(&r.p, coefs[i]);
         const int nchunks = (r.p.Ly + br.rows - 1) / br.rows;
+        std::vector<BatchItem>& dst = (r.p.bc_y == LBM_SHEAR_WALLS) ? wall_items : items;
         for (int c = 0; c < nchunks; ++c)
-            for (int st = 0; st < br.nstrips; ++st) items.push_back(BatchItem{i, st, c, 0});
+            for (int st = 0; st < br.nstrips; ++st) dst.push_back(BatchItem{i, st, c, 0});
     }
+    b->nitems_periodic = (int32_t)items.size();
+    items.insert(items.end(), wall_items.begin(), wall_items.end());
     char* p = base;
     b->d_runs = p;
     p += align_up((size_t)b->n * sizeof(BatchRun<double>));
@@ -707,15 +711,21 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
 
 lbm_status batch_launch(lbm_batch* b, hipStream_t s)
 {
-    hipError_t e;
-    if (b->precision == LBM_FP32_DEV)
-        e = launch_batch_step<float>(static_cast<const BatchRun<float>*>(b->d_runs),
-                                     static_cast<const StepCoef<float>*>(b->d_coefs), b->d_items, b->nitems, b->cur,
-                                     b->scheme, b->regularize, 1, s);
-    else
-        e = launch_batch_step<double>(static_cast<const BatchRun<double>*>(b->d_runs),
-                                      static_cast<const StepCoef<double>*>(b->d_coefs), b->d_items, b->nitems, b->cur,
-                                      b->scheme, b->regularize, 1, s);
+    // periodic items first, then the items of runs with shear walls
+    const int32_t n_per = b->nitems_periodic, n_wall = b->nitems - b->nitems_periodic;
+    hipError_t e = hipSuccess;
+    for (int walls = 0; walls < 2 && e == hipSuccess; ++walls) {
+        const BatchItem* items = b->d_items + (walls ? n_per : 0);
+        const int32_t n = walls ? n_wall : n_per;
+        if (b->precision == LBM_FP32_DEV)
+            e = launch_batch_step<float>(static_cast<const BatchRun<float>*>(b->d_runs),
+                                         static_cast<const StepCoef<float>*>(b->d_coefs), items, n, b->cur,
+                                         b->scheme, b->regularize, walls, 1, s);
+        else
+            e = launch_batch_step<double>(static_cast<const BatchRun<double>*>(b->d_runs),
+                                          static_cast<const StepCoef<double>*>(b->d_coefs), items, n, b->cur,
+                                          b->scheme, b->regularize, walls, 1, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "batch step launch");
     b->cur ^= 1;
     return LBM_OK;

@@ -104,12 +104,12 @@ struct Launch {
 
 // Host launchers (lbm_kernels.hip).
 template <typename R>
-hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int waves_per_group,
+hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int walls, int waves_per_group,
                        hipStream_t s);
 template <typename R>
 hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coefs,
                              const BatchItem* d_items, int32_t nitems, int32_t cur, int scheme,
-                             int regularize, int waves_per_group, hipStream_t s);
+                             int regularize, int walls, int waves_per_group, hipStream_t s);
 template <typename R>
 hipError_t launch_init(R* f, const StepCoef<R>* coef, const double* rho, const double* ux,
                        const double* uy, int64_t n, hipStream_t s);

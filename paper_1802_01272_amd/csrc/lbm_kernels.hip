@@ -86,6 +86,39 @@ __device__ __forceinline__ R upwind_x(R v)
     else return from_right(v);
 }
 
+// Raw buffer access: a field is addressed through two buffer descriptors
+// (planes 0-7 and 8-15), a per-lane 32-bit byte offset inside the plane and a
+// per-plane scalar byte offset, so no 64-bit address arithmetic runs on the
+// vector units.  Requires 8 planes to span less than 4 GiB.
+struct FieldRsrc {
+    __amdgpu_buffer_rsrc_t half[2];
+};
+template <typename R>
+__device__ __forceinline__ FieldRsrc make_field_rsrc(const R* base, int64_t plane)
+{
+    FieldRsrc f;
+    f.half[0] = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, -1, 0x00020000);
+    f.half[1] = __builtin_amdgcn_make_buffer_rsrc((void*)(base + 8 * plane), (short)0, -1, 0x00020000);
+    return f;
+}
+__device__ __forceinline__ void buf_load(float& v, const FieldRsrc& f, int k, uint32_t voff, uint32_t pbytes)
+{
+    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0));
+}
+__device__ __forceinline__ void buf_load(double& v, const FieldRsrc& f, int k, uint32_t voff, uint32_t pbytes)
+{
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0));
+}
+__device__ __forceinline__ void buf_store(float v, const FieldRsrc& f, int k, uint32_t voff, uint32_t pbytes)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0);
+}
+__device__ __forceinline__ void buf_store(double v, const FieldRsrc& f, int k, uint32_t voff, uint32_t pbytes)
+{
+    using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(f.half[0], 0u, 0u, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0);
+}
+
 // minmod(a, b) = median(a, b, 0): 0 when the signs differ, else the smaller one
 __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 __device__ __forceinline__ double minmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
@@ -112,7 +145,7 @@ template <typename R> struct G5W {
 // and the row finished (and stored, for t >= 4) is j = r - 2.  Per velocity,
 // the ring holds f at rows j-1, j, j+1 and the new row j+2.
 
-template <typename R, int SCHEME, bool REG>
+template <typename R, int SCHEME, bool REG, bool WALLS>
 __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restrict__ fout,
                                            const StepCoef<R>* __restrict__ C,
                                            const int Lx, const int Ly, const int64_t plane,
@@ -123,30 +156,40 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     int col = (strip * STRIP - HALO + lane) % Lx;
     if (col < 0) col += Lx;
     const bool out_lane = lane >= HALO && lane < WAVE - HALO && (strip * STRIP + lane - HALO) < Lx;
-    const int walls = C->walls;
     // rows y0-2 .. y1+1 are read; the loop runs in groups of four (the ring
     // period), and the few extra rows of the last group are computed, not stored
     const int niter = (y1 - y0) + 4;
     const int niter4 = (niter + 3) & ~3;
+    const FieldRsrc src = make_field_rsrc(fin, plane);
+    const FieldRsrc dst = make_field_rsrc(fout, plane);
+    const uint32_t pbytes = (uint32_t)(plane * (int64_t)sizeof(R));
 
-    auto load_row = [&](int r, R (&v)[16]) {
-        if (walls && (r < 0 || r >= Ly)) {
-            const R* g = (r < 0) ? C->ghost_lo : C->ghost_hi;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = g[k];
-        } else {
-            int rr = r % Ly;
-            if (rr < 0) rr += Ly;
-            // uniform plane base + 32-bit byte offset (a plane is < 4 GiB)
-            const R* base = fin + (int64_t)rr * Lx + col;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = base[k * plane];
+    // where row r comes from: a lattice row (wrapped periodically), or with
+    // walls one of the two ghost-row states (-1 below, +1 above)
+    auto row_src = [&](int r, uint32_t& voff, int& ghost) {
+        ghost = 0;
+        if constexpr (WALLS) {
+            if (r < 0) ghost = -1;
+            else if (r >= Ly) ghost = 1;
         }
+        int rr = r % Ly;
+        if (rr < 0) rr += Ly;
+        voff = ((uint32_t)rr * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
+    };
+    auto load_one = [&](int k, uint32_t voff, int ghost, R& v) {
+        if constexpr (WALLS) {
+            if (ghost) {
+                v = (ghost < 0) ? C->ghost_lo[k] : C->ghost_hi[k];
+                return;
+            }
+        }
+        buf_load(v, src, k, voff, pbytes);
     };
 
-    // Ring of four rows per velocity.  At phase P (= t mod 4) B[P] receives
-    // the new row r, and B[P+1], B[P+2], B[P+3] (mod 4) hold rows j-1, j, j+1
-    // of the output row j = r - 2; roles move by index, never by copying.
+    // Ring of four rows per velocity.  At phase P (= t mod 4) B[P] holds the
+    // new row r, and B[P+1], B[P+2], B[P+3] (mod 4) hold rows j-1, j, j+1 of
+    // the output row j = r - 2; roles move by index, never by copying.  Row
+    // r+1 is loaded during phase P into B[P+1] once row j-1 has been used.
     R B[4][16];
     // carries per velocity: the upwind x-difference D1 of the row the CTU1
     // part reuses, and for CTU2 Y' at row j and dX = X'_{i+1} - X'_i at row
@@ -164,10 +207,14 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) cD1[k] = cY[k] = cdX[k] = R(0);
+    {
+        uint32_t voff;
+        int ghost;
+        row_src(y0 - 2, voff, ghost);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) load_one(k, voff, ghost, B[0][k]);
+    }
 
-    // the next row is loaded one row ahead (software pipelining)
-    R NX[16];
-    load_row(y0 - 2, NX);
     auto body = [&](auto ph, const int t) {
         constexpr int P = decltype(ph)::value;
         constexpr int iN = P, iM1 = (P + 1) & 3, i0 = (P + 2) & 3, iP1 = (P + 3) & 3;
@@ -176,29 +223,23 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         R(&f0)[16] = B[i0];
         R(&fp1)[16] = B[iP1];
         const int r = y0 - 2 + t;
+        const bool ghost = WALLS && (r < 0 || r >= Ly);
+        // Row j-1 is only needed through D2 = f(j-1) - f(j) of the velocities
+        // with s_y > 0: form those, then load row r+1 into its slot B[iM1]
+        // before any store of this row (loads and stores share one in-order
+        // completion counter, so the next row's wait then never waits on
+        // this row's stores).
+        R D2m[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) cur[k] = NX[k];
-        load_row(r + 1, NX);
-        const bool ghost = walls && (r < 0 || r >= Ly);
-
-        // moments of the output row j = r - 2 (independent of the new row, so
-        // they overlap its loads): u = sum f xi / rho, a2 = sum f (xi xi - I)
-        // (w_k rho_ref drops out of both)
-        N jx = 0, jy = 0, axx = 0, axy = 0, ayy = 0;
-        static_for<0, 4>([&](auto gc) {
-            constexpr int G = decltype(gc)::value;
-            constexpr N qx = group_qx(G), qy = group_qy(G);
-            const N d0 = f0[4 * G], d1 = f0[4 * G + 1], d2 = f0[4 * G + 2], d3 = f0[4 * G + 3];
-            const N see = (d0 + d1) + (d2 + d3);
-            const N soe = (d0 - d1) - (d2 - d3);
-            const N seo = (d0 + d1) - (d2 + d3);
-            const N soo = (d0 - d1) + (d2 - d3);
-            jx += qx * soe;
-            jy += qy * seo;
-            axx += (qx * qx - 1.0) * see;
-            ayy += (qy * qy - 1.0) * see;
-            axy += (qx * qy) * soo;
-        });
+        for (int k = 0; k < 16; ++k)
+            if (sign_y(k) > 0) D2m[k] = fm1[k] - f0[k];
+        {
+            uint32_t nvoff;
+            int nghost;
+            row_src(r + 1, nvoff, nghost);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) load_one(k, nvoff, nghost, fm1[k]);
+        }
 
         // --- regularization of the new row (Eq. ereg): project onto the Hermite
         // space of order <= 3.  Linear in f and exact on w_k rho_ref, so it
@@ -305,6 +346,24 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         }
 
         // --- node quantities of the output row j = r - 2 ------------------------
+        // moments of the output row: u = sum f xi / rho, a2 = sum f (xi xi - I)
+        // (w_k rho_ref drops out of both)
+        N jx = 0, jy = 0, axx = 0, axy = 0, ayy = 0;
+        static_for<0, 4>([&](auto gc) {
+            constexpr int G = decltype(gc)::value;
+            constexpr N qx = group_qx(G), qy = group_qy(G);
+            const N d0 = f0[4 * G], d1 = f0[4 * G + 1], d2 = f0[4 * G + 2], d3 = f0[4 * G + 3];
+            const N see = (d0 + d1) + (d2 + d3);
+            const N soe = (d0 - d1) - (d2 - d3);
+            const N seo = (d0 + d1) - (d2 + d3);
+            const N soo = (d0 - d1) + (d2 - d3);
+            jx += qx * soe;
+            jy += qy * seo;
+            axx += (qx * qx - 1.0) * see;
+            ayy += (qy * qy - 1.0) * see;
+            axy += (qx * qy) * soo;
+        });
+
         const N ds_j = ds_m2;
         const N rho_j = C->rho0 + ds_j;
         const N inv_rho = 1.0 / rho_j;
@@ -336,7 +395,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         }
 
         const bool store_row = t >= 4 && r - 2 < y1;
-        R* const orow = fout + (int64_t)(r - 2) * Lx + col;
+        const uint32_t soff = ((uint32_t)(r - 2) * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
         const N dtt = C->dt_tau;
 
         // collision + force increment w_k P_k - dt/tau d_k of velocity 4G+s,
@@ -387,7 +446,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     const R rx = fj - from_left(fj);          // R^x at row j
                     const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
                     const R D1 = (SX > 0) ? -rx : rxu;
-                    const R D2 = fm1[K] - fj;
+                    const R D2 = D2m[K];
                     inc = C->a[MX] * D1 + C->a[MY] * D2 + C->ab[MX][MY] * (cD1[K] - D1);
                     cD1[K] = D1;
                     if constexpr (SCHEME == 2) {
@@ -427,8 +486,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 if constexpr (EARLY) coll = coll_all[K];
                 else coll = (R)poly[decltype(sc)::value];
                 const R fnew = fj + (inc + coll);
-                if (store_row && out_lane)
-                    orow[K * plane] = fnew;
+                if (store_row && out_lane) buf_store(fnew, dst, K, soff, pbytes);
             });
         });
     };
@@ -462,7 +520,7 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nblocks)
 // no spills to memory); the next row is prefetched to cover load latency.
 template <typename R> struct WavesPerEU { static constexpr int value = 1; };
 
-template <typename R, int SCHEME, bool REG>
+template <typename R, int SCHEME, bool REG, bool WALLS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::value))) void step_kernel(const R* __restrict__ fin, R* __restrict__ fout,
                                                    const StepCoef<R>* __restrict__ coef,
                                                    int Lx, int Ly, int64_t plane, int rows,
@@ -476,10 +534,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
     const int chunk = wave / nstrips, strip = wave - chunk * nstrips;
     const int y0 = chunk * rows;
     const int y1 = min(y0 + rows, Ly);
-    strip_step<R, SCHEME, REG>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1);
+    strip_step<R, SCHEME, REG, WALLS>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1);
 }
 
-template <typename R, int SCHEME, bool REG>
+template <typename R, int SCHEME, bool REG, bool WALLS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::value))) void batch_step_kernel(const BatchRun<R>* __restrict__ runs,
                                                          const StepCoef<R>* __restrict__ coefs,
                                                          const BatchItem* __restrict__ items,
@@ -493,7 +551,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
     const BatchRun<R> run = runs[it.run];
     const int y0 = it.chunk * run.rows;
     const int y1 = min(y0 + run.rows, run.Ly);
-    strip_step<R, SCHEME, REG>(run.f[cur], run.f[cur ^ 1], coefs + it.run,
+    strip_step<R, SCHEME, REG, WALLS>(run.f[cur], run.f[cur ^ 1], coefs + it.run,
                                                               run.Lx, run.Ly, run.plane, it.strip, y0, y1);
 }
 
@@ -648,41 +706,51 @@ int grid_for(int64_t n, int block)
 // launchers
 
 template <typename R>
-hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int wpg, hipStream_t s)
+hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int walls, int wpg, hipStream_t s)
 {
     const int nchunks = (rv.Ly + rv.rows - 1) / rv.rows;
     const int nwaves = rv.nstrips * nchunks;
     const int nblocks = (nwaves + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
-#define LBM_LAUNCH(SC, RG)                                                                              \
-    hipLaunchKernelGGL((step_kernel<R, SC, RG>), grid, block, 0, s, rv.f_in, rv.f_out, rv.coef, rv.Lx, \
+#define LBM_LAUNCH(SC, RG, WL)                                                                              \
+    hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, 0, s, rv.f_in, rv.f_out, rv.coef, rv.Lx, \
                        rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
+#define LBM_LAUNCH_W(SC, RG)          \
+    if (walls) LBM_LAUNCH(SC, RG, true); \
+    else LBM_LAUNCH(SC, RG, false)
     if (scheme == 1) {
-        if (regularize) LBM_LAUNCH(1, true);
-        else LBM_LAUNCH(1, false);
+        if (regularize) LBM_LAUNCH_W(1, true);
+        else LBM_LAUNCH_W(1, false);
     } else {
-        if (regularize) LBM_LAUNCH(2, true);
-        else LBM_LAUNCH(2, false);
+        if (regularize) LBM_LAUNCH_W(2, true);
+        else LBM_LAUNCH_W(2, false);
     }
+#undef LBM_LAUNCH_W
 #undef LBM_LAUNCH
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coefs, const BatchItem* d_items,
-                             int32_t nitems, int32_t cur, int scheme, int regularize, int wpg, hipStream_t s)
+                             int32_t nitems, int32_t cur, int scheme, int regularize, int walls, int wpg,
+                             hipStream_t s)
 {
+    if (nitems <= 0) return hipSuccess;
     const int nblocks = (nitems + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
-#define LBM_LAUNCH(SC, RG) \
-    hipLaunchKernelGGL((batch_step_kernel<R, SC, RG>), grid, block, 0, s, d_runs, d_coefs, d_items, nitems, cur)
+#define LBM_LAUNCH(SC, RG, WL) \
+    hipLaunchKernelGGL((batch_step_kernel<R, SC, RG, WL>), grid, block, 0, s, d_runs, d_coefs, d_items, nitems, cur)
+#define LBM_LAUNCH_W(SC, RG)          \
+    if (walls) LBM_LAUNCH(SC, RG, true); \
+    else LBM_LAUNCH(SC, RG, false)
     if (scheme == 1) {
-        if (regularize) LBM_LAUNCH(1, true);
-        else LBM_LAUNCH(1, false);
+        if (regularize) LBM_LAUNCH_W(1, true);
+        else LBM_LAUNCH_W(1, false);
     } else {
-        if (regularize) LBM_LAUNCH(2, true);
-        else LBM_LAUNCH(2, false);
+        if (regularize) LBM_LAUNCH_W(2, true);
+        else LBM_LAUNCH_W(2, false);
     }
+#undef LBM_LAUNCH_W
 #undef LBM_LAUNCH
     return hipGetLastError();
 }
@@ -731,9 +799,9 @@ hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_
 }
 
 #define LBM_INSTANTIATE(R)                                                                                   \
-    template hipError_t launch_step<R>(const RunView<R>&, int, int, int, hipStream_t);                       \
+    template hipError_t launch_step<R>(const RunView<R>&, int, int, int, int, hipStream_t);                  \
     template hipError_t launch_batch_step<R>(const BatchRun<R>*, const StepCoef<R>*, const BatchItem*,       \
-                                             int32_t, int32_t, int, int, int, hipStream_t);                  \
+                                             int32_t, int32_t, int, int, int, int, hipStream_t);             \
     template hipError_t launch_init<R>(R*, const StepCoef<R>*, const double*, const double*, const double*, \
                                        int64_t, hipStream_t);                                                \
     template hipError_t launch_moments<R>(const R*, const StepCoef<R>*, double*, double*, double*, int64_t, \

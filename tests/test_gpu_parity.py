@@ -122,11 +122,15 @@ def test_one_step_edge_sizes(Lx, Ly, bc):
 
 @pytest.mark.parametrize("launch", [(1, 1), (3, 2), (7, 4), (64, 1), (256, 2)])
 def test_launch_shape_does_not_change_results(launch):
+    """Chunking rows differently changes nothing beyond rounding (a row's
+    position in the unrolled row loop may round a multiply-add differently);
+    a fixed launch shape is bitwise reproducible."""
     p = make_params(130, 45, 2, 1, 1)
     f = random_state(p, 40)
     base = gpu_step_from(p, f, nsteps=3, launch=(16, 2))
     got = gpu_step_from(p, f, nsteps=3, launch=launch)
-    assert np.array_equal(base, got)
+    assert rel_err(got, base) < 1e-14
+    assert np.array_equal(got, gpu_step_from(p, f, nsteps=3, launch=launch))
 
 
 # ------------------------------------------------------------ many steps
