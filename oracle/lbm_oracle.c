@@ -8,9 +8,12 @@
  * a time, in the order the paper introduces them, no blocking and no fusion.
  *
  * Readings of the paper taken here (the paper is silent, garbled or ambiguous):
- *  - The collision, force and advection terms are added in one explicit update
- *    with every term at time level n (Sec. II C 2, the CTU2 update formula); the
- *    same structure is used with CTU1.
+ *  - A time step is the two-step split of Sec. II C: advection of f^n first
+ *    (left-hand side of Eq. eBGK, by CTU1 or CTU2), then collision and force
+ *    (right-hand side) evaluated on the advected state f*.  The apparent
+ *    viscosities of Table apparentvisco, T (tau - dt/2) plus the numerical
+ *    part, identify this order; an update with every term at level n would
+ *    give T (tau + dt/2).
  *  - In the CTU2 limiter of S^y the printed ratio uses R^x; it is read as
  *    R^y_{i,j-s_y} / R^y_{i,j}, the symmetric counterpart of S^x.
  *  - In the transverse term of the x-flux the printed index pair of R^y is
@@ -24,8 +27,9 @@
  *    applies the 9-point isotropic gradient (w(1)=1/3, w(2)=1/12) to the
  *    9-point isotropic Laplacian (4*sum_nn + sum_diag - 20*centre)/6.
  *  - a^(2) in the force term is the second Hermite moment of f itself.
- *  - Regularization replaces f by f^eq + fhat^neq at every node at the start of
- *    each step, so that f itself stays in the Hermite space of order <= 3.
+ *  - Regularization replaces the advected f* by f^eq + fhat^neq at every node
+ *    before the collision, so that f itself stays in the Hermite space of
+ *    order <= 3.
  *  - Shear walls: ghost rows j = -2, -1 hold f^eq(rho_w, (-u_w, 0)) and rows
  *    j = Ly, Ly+1 hold f^eq(rho_w, (+u_w, 0)); x stays periodic.
  */
@@ -438,21 +442,47 @@ int orc_step_region(const orc_params* p, const double* f_in,
     orc_feq(T, p->rho_wall, +p->u_wall, 0.0, ghost + 16);
 
     const int nx = i1 - i0, ny = j1 - j0;
-    const int nEx = nx + 4, nEy = ny + 4;
+    const int nEx = nx + 4, nEy = ny + 4;          /* region + 2: stencil reach  */
+    const int nGx = nx + 8, nGy = ny + 8;          /* region + 4: + advection    */
     const size_t nE = (size_t)nEx * nEy, nR = (size_t)nx * ny;
+    const size_t nG = (size_t)nGx * nGy;
 
-    /* 1. gather the extended box; regularize lattice nodes if asked */
+    /* 1. gather f^n on the box extended by four nodes */
+    double* fG = malloc(sizeof(double) * 16 * nG);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if ((size_t)nGx * (size_t)nGy > 16384)
+#endif
+    for (int gy = 0; gy < nGy; ++gy)
+        for (int gx = 0; gx < nGx; ++gx) {
+            const int i = i0 + gx - 4, j = j0 + gy - 4;
+            for (int k = 0; k < 16; ++k)
+                fG[(size_t)k * nG + (size_t)gy * nGx + gx] = f_at(p, f_in, ghost, k, i, j);
+        }
+
+    /* 2. first step of the split: advection, f* = A_k(f^n), on the box
+     *    extended by two.  Ghost rows of the walls are boundary values and keep
+     *    their state.  Regularization (Eq. ereg) then replaces f* by
+     *    f^eq + fhat^neq at every lattice node. */
     double* fE = malloc(sizeof(double) * 16 * nE);
+    for (int k = 0; k < 16; ++k) {
+        if (p->scheme == 1) ctu1_literal(nGx, nGy, ds, dt, xx[k], xy[k], fG + (size_t)k * nG, fE + (size_t)k * nE);
+        else ctu2_flux(nGx, nGy, ds, dt, xx[k], xy[k], p->limiter, fG + (size_t)k * nG, fE + (size_t)k * nE);
+    }
+    free(fG);
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) if ((size_t)nEx * (size_t)nEy > 16384)
 #endif
     for (int ey = 0; ey < nEy; ++ey)
         for (int ex = 0; ex < nEx; ++ex) {
-            const int i = i0 + ex - 2, j = j0 + ey - 2;
-            double fn[16];
-            for (int k = 0; k < 16; ++k) fn[k] = f_at(p, f_in, ghost, k, i, j);
+            const int j = j0 + ey - 2;
             const int is_ghost = (p->bc_y == 1) && (j < 0 || j >= p->Ly);
-            if (p->regularize && !is_ghost) orc_regularize_node(T, fn);
+            double fn[16];
+            if (is_ghost) {
+                for (int k = 0; k < 16; ++k) fn[k] = ghost[(j < 0 ? 0 : 16) + k];
+            } else {
+                for (int k = 0; k < 16; ++k) fn[k] = fE[(size_t)k * nE + EIDX(ex, ey)];
+                if (p->regularize) orc_regularize_node(T, fn);
+            }
             for (int k = 0; k < 16; ++k) fE[(size_t)k * nE + EIDX(ex, ey)] = fn[k];
         }
 
@@ -518,14 +548,8 @@ int orc_step_region(const orc_params* p, const double* f_in,
             gy[r] = (py / ds) / rc + p->kappa * (ly / ds);
         }
 
-    /* 4. advection of every velocity */
-    double* A = malloc(sizeof(double) * 16 * nR);
-    for (int k = 0; k < 16; ++k) {
-        if (p->scheme == 1) ctu1_literal(nEx, nEy, ds, dt, xx[k], xy[k], fE + (size_t)k * nE, A + (size_t)k * nR);
-        else ctu2_flux(nEx, nEy, ds, dt, xx[k], xy[k], p->limiter, fE + (size_t)k * nE, A + (size_t)k * nR);
-    }
-
-    /* 5. f^{n+1} = A_k(f) - dt/tau (f - f^eq) + dt F_k */
+    /* 4. second step of the split: collision and force on the advected state,
+     *    f^{n+1} = f* - dt/tau (f* - f^eq(f*)) + dt F_k(f*) */
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) if ((size_t)nEx * (size_t)nEy > 16384)
 #endif
@@ -537,12 +561,12 @@ int orc_step_region(const orc_params* p, const double* f_in,
             orc_force(rho[e], ux[e], uy[e], gx[r], gy[r], &a2[3 * e], F);
             for (int k = 0; k < 16; ++k) {
                 const double fk = fE[(size_t)k * nE + e];
-                out[(size_t)k * nR + r] = A[(size_t)k * nR + r] - dt / p->tau * (fk - feq[k]) + dt * F[k];
+                out[(size_t)k * nR + r] = fk - dt / p->tau * (fk - feq[k]) + dt * F[k];
             }
         }
 
     free(fE); free(rho); free(ux); free(uy); free(a2);
-    free(phi); free(lap); free(gx); free(gy); free(A);
+    free(phi); free(lap); free(gx); free(gy);
     return 0;
 }
 

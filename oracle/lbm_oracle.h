@@ -75,7 +75,8 @@ void orc_advect(int Lx, int Ly, double ds, double dt, double cx, double cy,
 void orc_init(const orc_params* p, const double* rho, const double* ux,
               const double* uy, double* f);
 
-/* One full time step, f_in -> f_out (both 16*Lx*Ly). Returns 0 or -1. */
+/* One full time step, f_in -> f_out (both 16*Lx*Ly): advection of f_in,
+ * then collision and force on the advected state (Sec. II C). Returns 0 or -1. */
 int orc_step(const orc_params* p, const double* f_in, double* f_out);
 
 /* Several steps; f is updated in place. Returns 0 or -1. */
