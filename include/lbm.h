@@ -6,8 +6,9 @@
  *   V. Sofonea, T. Biciusca, S. Busuioc, V. E. Ambrus, G. Gonnella, A. Lamura,
  *   "Corner transport upwind lattice Boltzmann model for bubble cavitation",
  *   arXiv:1802.01272 (Phys. Rev. E 97, 023309, 2018)
- * by one explicit step per time increment:
- *   f_k^{n+1} = A_k(f^n) - (dt/tau)(f_k^n - f_k^eq) + dt F_k,
+ * by the two-step explicit split of Sec. II C per time increment: advection
+ * first, then collision and force on the advected state,
+ *   f*_k = A_k(f^n),   f_k^{n+1} = f*_k - (dt/tau)(f*_k - f_k^eq(f*)) + dt F_k(f*),
  * with the velocity set of Table "roots", the Hermite equilibrium of Eq.
  * (herfeq), the force term of Eq. (herforce) driven by the van der Waals
  * acceleration of Eq. (eder), the optional regularization of Eq. (ereg), and
@@ -71,7 +72,8 @@ typedef struct {
                              with kappa = 0 is the ideal gas, g = 0)             */
     double kappa;         /* surface-tension parameter of Eq. (eder), >= 0       */
     int32_t scheme;       /* 1 = CTU1, 2 = CTU2 with the MC limiter              */
-    int32_t regularize;   /* 0/1: replace f by f^eq + fhat^neq, Eq. (ereg)       */
+    int32_t regularize;   /* 0/1: replace the advected f* by f^eq + fhat^neq
+                             before the collision, Eq. (ereg)                  */
     int32_t precision;    /* LBM_FP64, or LBM_FP32_DEV: f_k - w_k rho_ref stored
                              and advected in FP32                                */
     double rho_ref;       /* rho_ref of the FP32 deviation storage, > 0          */
@@ -174,8 +176,9 @@ lbm_status lbm_set_f_device(lbm_run* run, const double* d_f, void* stream);
 lbm_status lbm_reduce(lbm_run* run, double rho_threshold, lbm_stats* out, void* stream);
 
 /* Launch shape: rows of the lattice each wavefront advances (>= 1) and
- * wavefronts per workgroup (1, 2 or 4).  Defaults come from lbm_autotune or
- * a built-in table. */
+ * wavefronts per workgroup (1, 2 or 4; at most 2 with FP64 storage, whose
+ * kernels use 24 KiB of LDS per wavefront).  LBM_EINVAL otherwise.  Defaults
+ * come from lbm_autotune or a built-in table. */
 lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per_group);
 lbm_status lbm_get_launch(const lbm_run* run, int32_t* rows_per_wave, int32_t* waves_per_group);
 

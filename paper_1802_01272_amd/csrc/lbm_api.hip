@@ -148,10 +148,19 @@ size_t run_bytes(const lbm_params* p)
 Launch default_launch(const lbm_params* p)
 {
     const int nstrips = (p->Lx + STRIP - 1) / STRIP;
-    int rows = 64;
+    int rows = 128;
     while (rows > 8 && (int64_t)nstrips * ((p->Ly + rows - 1) / rows) < 4096) rows /= 2;
     return Launch{rows, 2};
 }
+
+// LDS of a step workgroup: the kernels keep the advected rows that wait for
+// their collision there (FP64 storage); capped at 64 KiB per workgroup
+constexpr size_t MAX_STEP_LDS = 65536;
+size_t step_lds_bytes(const lbm_params* p, int wpg)
+{
+    return (size_t)wpg * (p->precision == LBM_FP32_DEV ? step_lds_per_wave<float>() : step_lds_per_wave<double>());
+}
+bool launch_fits(const lbm_params* p, int wpg) { return step_lds_bytes(p, wpg) <= MAX_STEP_LDS; }
 
 std::mutex g_tune_mutex;
 std::map<std::tuple<int, int, int, int, int>, Launch> g_tuned;  // (Lx, Ly, precision, scheme, regularize)
@@ -570,6 +579,8 @@ lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per
     if (rows_per_wave < 1) return fail(LBM_EINVAL, "rows_per_wave must be >= 1");
     if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
         return fail(LBM_EINVAL, "waves_per_group must be 1, 2 or 4");
+    if (!launch_fits(&run->p, waves_per_group))
+        return fail(LBM_EINVAL, "waves_per_group too large for the LDS of this storage precision (FP64: at most 2)");
     run->launch = Launch{rows_per_wave, waves_per_group};
     return LBM_OK;
 }
@@ -609,13 +620,14 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_ws, size_t ws_bytes, void* 
         if (e != hipSuccess) return hip_fail(e, "autotune init");
         HIP_TRY(hipStreamSynchronize(s), "autotune init");
     }
-    const int rows_c[] = {8, 16, 32, 48, 64, 96, 128, 192, 256};
+    const int rows_c[] = {8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512};
     const int wpg_c[] = {1, 2, 4};
     double best = 1e300;
     Launch bl = default_launch(p);
     for (int rows : rows_c) {
         if (rows > 2 * p->Ly && rows != rows_c[0]) continue;
         for (int wpg : wpg_c) {
+            if (!launch_fits(p, wpg)) continue;
             r.launch = Launch{rows, wpg};
             for (int w = 0; w < 2; ++w) {
                 st = step_once(&r, s);

@@ -30,10 +30,22 @@ __host__ __device__ constexpr double xi_x(int k) { return sign_x(k) * group_qx(k
 __host__ __device__ constexpr double xi_y(int k) { return sign_y(k) * group_qy(k >> 2); }
 __host__ __device__ constexpr double weight(int k) { return group_w(k >> 2); }
 
-// Output columns per wavefront: 64 lanes minus a 2-lane halo on each side.
+// Output columns per wavefront: 64 lanes minus a 4-lane halo on each side
+// (advection reaches two columns, the force stencils on the advected density
+// two more).
 constexpr int WAVE = 64;
-constexpr int HALO = 2;
+constexpr int HALO = 4;
 constexpr int STRIP = WAVE - 2 * HALO;
+
+// The step kernels hold the advected rows that wait for their collision (three
+// rows of 16 values per lane) in LDS for FP64 storage, in registers for FP32.
+template <typename R> struct PendingInLds { static constexpr bool value = sizeof(R) == 8; };
+constexpr int PENDING_ROWS = 3;
+template <typename R>
+constexpr size_t step_lds_per_wave()
+{
+    return PendingInLds<R>::value ? (size_t)PENDING_ROWS * 16 * WAVE * sizeof(R) : 0;
+}
 
 // ---------------------------------------------------------------------------
 // Per-run coefficients, prepared on the host in the storage precision R and

@@ -1,23 +1,28 @@
 // lbm_kernels.hip -- gfx950 kernels of the CTU lattice Boltzmann stepper.
 //
 // One time step of the 16-velocity, third-order isothermal lattice Boltzmann
-// model of Sofonea et al. (arXiv:1802.01272):
-//   f_k^{n+1} = A_k(f^n) - (dt/tau)(f_k - f_k^eq) + dt F_k        (Sec. II C 2)
+// model of Sofonea et al. (arXiv:1802.01272), split in two explicit steps as
+// in Sec. II C: advection first, then collision and force on the advected
+// state,
+//   f*_k = A_k(f^n),   f_k^{n+1} = f*_k - (dt/tau)(f*_k - f_k^eq) + dt F_k,
 // with f^eq of Eq. (herfeq), F_k of Eq. (herforce), the acceleration of
-// Eq. (eder) from 25-point stencils (Sec. II B), optional regularization
-// (Eq. ereg) and CTU1 (Eq. ctueq) or CTU2 (Sec. II C 2) advection A_k.
+// Eq. (eder) from 25-point stencils on the advected density (Sec. II B),
+// optional regularization of f* (Eq. ereg) and CTU1 (Eq. ctueq) or CTU2
+// (Sec. II C 2) advection A_k.
 //
 // Design (MI355X / CDNA4):
-//  * A wavefront owns a strip of 64 consecutive columns (60 written, 2 halo
-//    columns each side, periodic in x) and marches up a chunk of rows.  Every
-//    x-neighbour access is a DPP wave shift (lane i reads lane i -+ 1); every
-//    y-neighbour is a register carried from earlier rows.  No LDS, no
-//    barriers: each wavefront is independent.
-//  * Each loaded row is used for everything at once: its density feeds the
-//    force stencils two rows behind, its f_k feed the upwind differences, and
-//    the output row two rows behind is finished and stored.  Each value of f
-//    is read from HBM once per step (plus the 4-column and 4-row halo) and
-//    written once.
+//  * A wavefront owns a strip of 64 consecutive columns (56 written, 4 halo
+//    columns each side, periodic in x: advection reaches two columns, the
+//    force stencils on the advected density two more) and marches up a chunk
+//    of rows.  Every x-neighbour access is a DPP wave shift (lane i reads
+//    lane i -+ 1); every y-neighbour is a register carried from earlier rows.
+//    No barriers: each wavefront is independent.
+//  * One pass per step: each loaded row of f^n feeds the advection of the row
+//    two behind it; the advected row's density feeds the force stencils, and
+//    the row two behind that is collided and stored.  Each value of f is read
+//    from HBM once per step (plus the 8-column and 8-row halo) and written
+//    once.  The advected rows that wait for their collision stay on chip, in
+//    registers (FP32) or in LDS (FP64).
 //  * CTU2 is evaluated in an equivalent rearranged form: the CTU1 bilinear
 //    update (Eq. ctueq) plus, per node, the limited corrections X = S^x and
 //    Y = S^y (division-free MC limiter) computed once per node and blended
@@ -31,10 +36,10 @@
 //  * Storage is FP64, or FP32 deviations d_k = f_k - w_k rho_ref (advection
 //    is linear and preserves constants, so it acts on d_k directly).  The
 //    advective increment A_k(f) - f is formed from upwind differences, so it
-//    is exactly zero on a constant field in any precision, and it is added to
-//    f last.  Node-local arithmetic (moments, stencils, collision and force)
-//    is FP64 in both storage modes: in FP32 its rounding acts as a small
-//    systematic forcing that accumulates step after step.
+//    is exactly zero on a constant field in any precision.  Node-local
+//    arithmetic (moments, stencils, collision and force) is FP64 in both
+//    storage modes: in FP32 its rounding acts as a small systematic forcing
+//    that accumulates step after step.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -119,6 +124,14 @@ __device__ __forceinline__ void buf_store(double v, const FieldRsrc& f, int k, u
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0);
 }
 
+// compile-time choice between two arrays of one type
+template <bool FIRST, typename T>
+__device__ __forceinline__ T& pick(T& a, T& b)
+{
+    if constexpr (FIRST) return a;
+    else return b;
+}
+
 // minmod(a, b) = median(a, b, 0): 0 when the signs differ, else the smaller one
 __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 __device__ __forceinline__ double minmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
@@ -141,24 +154,29 @@ template <typename R> struct G5W {
 // ----------------------------------------------------------------------------
 // The fused step for one wavefront strip.
 //
-// Rows are processed in order; at iteration t the newest row is r = y0 - 2 + t
-// and the row finished (and stored, for t >= 4) is j = r - 2.  Per velocity,
-// the ring holds f at rows j-1, j, j+1 and the new row j+2.
+// Rows are processed in order.  At iteration t the newest loaded row is
+// r = y0 - 4 + t; row a = r - 2 is advected (it needs f at rows a-2 .. a+2),
+// and row o = a - 2 is collided and stored (for t >= 8): its force stencils
+// need the advected density of rows o-2 .. o+2.  Per velocity, the ring B
+// holds f^n at rows a-1, a, a+1 and the new row a+2; the ring S holds the
+// advected rows a-2, a-1 and a until row a-2 is collided.
 
 template <typename R, int SCHEME, bool REG, bool WALLS>
 __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restrict__ fout,
                                            const StepCoef<R>* __restrict__ C,
                                            const int Lx, const int Ly, const int64_t plane,
-                                           const int strip, const int y0, const int y1)
+                                           const int strip, const int y0, const int y1,
+                                           R* __restrict__ pend)
 {
+    constexpr bool PEND_LDS = PendingInLds<R>::value;
     using N = double;  // node-local arithmetic (moments, stencils, collision)
     const int lane = threadIdx.x & (WAVE - 1);
     int col = (strip * STRIP - HALO + lane) % Lx;
     if (col < 0) col += Lx;
     const bool out_lane = lane >= HALO && lane < WAVE - HALO && (strip * STRIP + lane - HALO) < Lx;
-    // rows y0-2 .. y1+1 are read; the loop runs in groups of four (the ring
+    // rows y0-4 .. y1+3 are read; the loop runs in groups of four (the ring
     // period), and the few extra rows of the last group are computed, not stored
-    const int niter = (y1 - y0) + 4;
+    const int niter = (y1 - y0) + 8;
     const int niter4 = (niter + 3) & ~3;
     const FieldRsrc src = make_field_rsrc(fin, plane);
     const FieldRsrc dst = make_field_rsrc(fout, plane);
@@ -176,33 +194,52 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         if (rr < 0) rr += Ly;
         voff = ((uint32_t)rr * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
     };
+    // The two ghost-row states are read per use through a buffer descriptor
+    // over the coefficients (vector loads), so that their 32 values are not
+    // hoisted into registers for the whole march.
+    const __amdgpu_buffer_rsrc_t coef_rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)C, (short)0, (int)sizeof(StepCoef<R>), 0x00020000);
+    auto ghost_value = [&](int k, bool low) -> R {
+        const uint32_t off = (uint32_t)(low ? offsetof(StepCoef<R>, ghost_lo) : offsetof(StepCoef<R>, ghost_hi))
+                           + (uint32_t)k * (uint32_t)sizeof(R);
+        if constexpr (sizeof(R) == 4)
+            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(coef_rsrc, off, 0u, 0));
+        else
+            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(coef_rsrc, off, 0u, 0));
+    };
     auto load_one = [&](int k, uint32_t voff, int ghost, R& v) {
         if constexpr (WALLS) {
             if (ghost) {
-                v = (ghost < 0) ? C->ghost_lo[k] : C->ghost_hi[k];
+                v = ghost_value(k, ghost < 0);
                 return;
             }
         }
         buf_load(v, src, k, voff, pbytes);
     };
 
-    // Ring of four rows per velocity.  At phase P (= t mod 4) B[P] holds the
-    // new row r, and B[P+1], B[P+2], B[P+3] (mod 4) hold rows j-1, j, j+1 of
-    // the output row j = r - 2; roles move by index, never by copying.  Row
-    // r+1 is loaded during phase P into B[P+1] once row j-1 has been used.
+    // Rings of four rows per velocity, indexed by phase P (= t mod 4): B[P]
+    // holds the new row r, and B[P+1], B[P+2], B[P+3] (mod 4) hold rows a-1,
+    // a, a+1; S[P] receives the advected row a, and S[P+2], S[P+3] hold the
+    // advected rows a-2, a-1.  Roles move by index, never by copying.  Row
+    // r+1 is loaded during phase P into B[P+1] once row a-1 has been used.
+    // With PEND_LDS the advected rows wait instead in three LDS slots of this
+    // wavefront (slot t mod 3 receives row a; each lane reads back only what
+    // it wrote, so no barrier is needed).
     R B[4][16];
+    R S[4][16];
     // carries per velocity: the upwind x-difference D1 of the row the CTU1
-    // part reuses, and for CTU2 Y' at row j and dX = X'_{i+1} - X'_i at row
-    // j-1 (s_y > 0) or j (s_y < 0)
+    // part reuses, and for CTU2 Y' at row a and dX = X'_{i+1} - X'_i at row
+    // a-1 (s_y > 0) or a (s_y < 0)
     R cD1[16], cY[16], cdX[16];
-    // per-row stencil rings (same indexing by phase): density deviation sums
-    // and their x-sums (row r), Laplacian rows and their x-differences and
-    // x-sums (row r-1), pending 24-neighbour gradient sums (rows r-2 .. r+1)
+    // per-row stencil rings (same indexing by phase): advected density
+    // deviation sums and their x-sums (row a), Laplacian rows and their
+    // x-differences and x-sums (row a-1), pending 24-neighbour gradient sums
+    // (rows a-2 .. a+1)
     N dsr[4], hsr[4], Lr[4], dLr[4], sLr[4], ax[4], ay[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) B[i][k] = R(0);
+        for (int k = 0; k < 16; ++k) B[i][k] = S[i][k] = R(0);
         dsr[i] = hsr[i] = Lr[i] = dLr[i] = sLr[i] = ax[i] = ay[i] = N(0);
     }
 #pragma unroll
@@ -210,7 +247,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     {
         uint32_t voff;
         int ghost;
-        row_src(y0 - 2, voff, ghost);
+        row_src(y0 - 4, voff, ghost);
 #pragma unroll
         for (int k = 0; k < 16; ++k) load_one(k, voff, ghost, B[0][k]);
     }
@@ -222,9 +259,13 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         R(&fm1)[16] = B[iM1];
         R(&f0)[16] = B[i0];
         R(&fp1)[16] = B[iP1];
-        const int r = y0 - 2 + t;
-        const bool ghost = WALLS && (r < 0 || r >= Ly);
-        // Row j-1 is only needed through D2 = f(j-1) - f(j) of the velocities
+        R fsl[16];
+        R(&fs)[16] = pick<PEND_LDS>(fsl, S[iN]);   // advected row a (written here)
+        const int r = y0 - 4 + t;
+        const int a = r - 2;
+        const int o = a - 2;
+        const bool ghost_a = WALLS && (a < 0 || a >= Ly);
+        // Row a-1 is only needed through D2 = f(a-1) - f(a) of the velocities
         // with s_y > 0: form those, then load row r+1 into its slot B[iM1]
         // before any store of this row (loads and stores share one in-order
         // completion counter, so the next row's wait then never waits on
@@ -241,22 +282,81 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             for (int k = 0; k < 16; ++k) load_one(k, nvoff, nghost, fm1[k]);
         }
 
-        // --- regularization of the new row (Eq. ereg): project onto the Hermite
-        // space of order <= 3.  Linear in f and exact on w_k rho_ref, so it
-        // acts on the stored deviations as they are.
+        // --- first step of the split: advection of row a -----------------------
+        static_for<0, 16>([&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            constexpr int SX = sign_x(K), SY = sign_y(K), MX = mag_x(K), MY = mag_y(K);
+            const R fj = f0[K];
+            // advective increment A_k(f) - f from upwind differences (exact on
+            // constants): with D1 = f(i - s_x) - f(i) on row a and on the row
+            // upwind in y, D2 = f(a - s_y) - f(a), the CTU1 part is
+            // a D1 + b D2 + a b (D1(a - s_y) - D1(a)).  D1 of the row that is
+            // reused one row later is carried in cD1.
+            R inc;
+            if constexpr (SY > 0) {
+                const R rx = fj - from_left(fj);          // R^x at row a
+                const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
+                const R D1 = (SX > 0) ? -rx : rxu;
+                const R D2 = D2m[K];
+                inc = C->a[MX] * D1 + C->a[MY] * D2 + C->ab[MX][MY] * (cD1[K] - D1);
+                cD1[K] = D1;
+                if constexpr (SCHEME == 2) {
+                    // X' at row a and its x-difference; dX of row a-1 is carried
+                    const R X = mc_half(rx, rxu);
+                    const R dXj = from_right(X) - X;
+                    // Y' at row a+1 (ratio with R^y of row a = -D2); Y' of row a is carried
+                    const R Y1 = mc_half(fp1[K] - fj, -D2);
+                    const R dY = Y1 - cY[K];
+                    inc += C->xs1[MX][MY] * dXj + C->xs2[MX][MY] * cdX[K] + C->ys1[MX][MY] * dY
+                         + C->ys2[MX][MY] * upwind_x<SX>(dY);
+                    cdX[K] = dXj;
+                    cY[K] = Y1;
+                }
+            } else {
+                const R fjp = fp1[K];
+                const R rx = fjp - from_left(fjp);        // R^x at row a+1
+                const R rxu = upwind_x<SX>(rx);
+                const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row a+1
+                const R D2 = fjp - fj;
+                inc = C->a[MX] * cD1[K] + C->a[MY] * D2 + C->ab[MX][MY] * (D1p - cD1[K]);
+                cD1[K] = D1p;
+                if constexpr (SCHEME == 2) {
+                    // X' at row a+1 and its x-difference; dX of row a is carried
+                    const R X = mc_half(rx, rxu);
+                    const R dXjp = from_right(X) - X;
+                    // Y' at row a+1 (ratio with R^y of row a+2); Y' of row a is carried
+                    const R Y1 = mc_half(D2, cur[K] - fjp);
+                    const R dY = Y1 - cY[K];
+                    inc += C->xs1[MX][MY] * cdX[K] + C->xs2[MX][MY] * dXjp + C->ys1[MX][MY] * dY
+                         + C->ys2[MX][MY] * upwind_x<SX>(dY);
+                    cdX[K] = dXjp;
+                    cY[K] = Y1;
+                }
+            }
+            fs[K] = fj + inc;
+        });
+        // wall ghost rows are boundary values: they keep their state
+        if (ghost_a) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) fs[k] = ghost_value(k, a < 0);
+        }
+
+        // --- regularization of the advected row (Eq. ereg): project onto the
+        // Hermite space of order <= 3.  Linear in f and exact on w_k rho_ref,
+        // so it acts on the stored deviations as they are.
         if constexpr (REG) {
-            if (!ghost) {
-                N a[4][4];  // a[m][n] = sum_k d_k He_m(xi_x) He_n(xi_y), m + n <= 3
+            if (!ghost_a) {
+                N c[4][4];  // c[m][n] = sum_k d_k He_m(xi_x) He_n(xi_y), m + n <= 3
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
-                    for (int n = 0; n < 4; ++n) a[m][n] = N(0);
+                    for (int n = 0; n < 4; ++n) c[m][n] = N(0);
                 static_for<0, 4>([&](auto gc) {
                     constexpr int G = decltype(gc)::value;
                     constexpr N qx = group_qx(G), qy = group_qy(G);
                     constexpr N hx[4] = {1.0, qx, qx * qx - 1.0, qx * qx * qx - 3.0 * qx};
                     constexpr N hy[4] = {1.0, qy, qy * qy - 1.0, qy * qy * qy - 3.0 * qy};
-                    const N d0 = cur[4 * G], d1 = cur[4 * G + 1], d2 = cur[4 * G + 2], d3 = cur[4 * G + 3];
+                    const N d0 = fs[4 * G], d1 = fs[4 * G + 1], d2 = fs[4 * G + 2], d3 = fs[4 * G + 3];
                     const N see = (d0 + d1) + (d2 + d3);   // even in x, even in y
                     const N soe = (d0 - d1) - (d2 - d3);   // odd in x
                     const N seo = (d0 + d1) - (d2 + d3);   // odd in y
@@ -266,53 +366,57 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
 #pragma unroll
                         for (int n = 0; n < 4 - m; ++n) {
                             const N s = (m & 1) ? ((n & 1) ? soo : soe) : ((n & 1) ? seo : see);
-                            a[m][n] += hx[m] * hy[n] * s;
+                            c[m][n] += hx[m] * hy[n] * s;
                         }
                 });
-                // coefficients of the reconstruction w_k sum a_mn He_m He_n / (m! n!)
+                // coefficients of the reconstruction w_k sum c_mn He_m He_n / (m! n!)
                 constexpr N fact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
-                    for (int n = 0; n < 4 - m; ++n) a[m][n] *= fact[m] * fact[n];
+                    for (int n = 0; n < 4 - m; ++n) c[m][n] *= fact[m] * fact[n];
                 static_for<0, 4>([&](auto gc) {
                     constexpr int G = decltype(gc)::value;
                     constexpr N qx = group_qx(G), qy = group_qy(G), w = group_w(G);
                     constexpr N hx[4] = {1.0, qx, qx * qx - 1.0, qx * qx * qx - 3.0 * qx};
                     constexpr N hy[4] = {1.0, qy, qy * qy - 1.0, qy * qy * qy - 3.0 * qy};
-                    const N EE = a[0][0] + a[2][0] * hx[2] + a[0][2] * hy[2];
-                    const N OE = a[1][0] * hx[1] + a[3][0] * hx[3] + a[1][2] * (hx[1] * hy[2]);
-                    const N EO = a[0][1] * hy[1] + a[0][3] * hy[3] + a[2][1] * (hx[2] * hy[1]);
-                    const N OO = a[1][1] * (hx[1] * hy[1]);
+                    const N EE = c[0][0] + c[2][0] * hx[2] + c[0][2] * hy[2];
+                    const N OE = c[1][0] * hx[1] + c[3][0] * hx[3] + c[1][2] * (hx[1] * hy[2]);
+                    const N EO = c[0][1] * hy[1] + c[0][3] * hy[3] + c[2][1] * (hx[2] * hy[1]);
+                    const N OO = c[1][1] * (hx[1] * hy[1]);
                     const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
-                    cur[4 * G + 0] = (R)(w * (Pp + Sp));   // (+,+)
-                    cur[4 * G + 1] = (R)(w * (Pm - Sm));   // (-,+)
-                    cur[4 * G + 2] = (R)(w * (Pp - Sp));   // (-,-)
-                    cur[4 * G + 3] = (R)(w * (Pm + Sm));   // (+,-)
+                    fs[4 * G + 0] = (R)(w * (Pp + Sp));   // (+,+)
+                    fs[4 * G + 1] = (R)(w * (Pm - Sm));   // (-,+)
+                    fs[4 * G + 2] = (R)(w * (Pp - Sp));   // (-,-)
+                    fs[4 * G + 3] = (R)(w * (Pm + Sm));   // (+,-)
                 });
             }
         }
 
-        // --- density of the new row and the force stencils (Eq. eder) --------
+        // --- advected density of row a and the force stencils (Eq. eder) -----
         N ds_r;
-        if (ghost) {
-            ds_r = ((r < 0) ? C->ghost_rho_lo : C->ghost_rho_hi) - C->rho0;
+        if (ghost_a) {
+            ds_r = ((a < 0) ? C->ghost_rho_lo : C->ghost_rho_hi) - C->rho0;
         } else {
-            ds_r = (N)cur[0];
+            ds_r = (N)fs[0];
 #pragma unroll
-            for (int k = 1; k < 16; ++k) ds_r += (N)cur[k];
+            for (int k = 1; k < 16; ++k) ds_r += (N)fs[k];
+        }
+        if constexpr (PEND_LDS) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) pend[((t % PENDING_ROWS) * 16 + k) * WAVE + lane] = fs[k];
         }
         const N rho_r = C->rho0 + ds_r;
         // p^i - p^w = rho T - rho T/(1 - b rho) + a rho^2 = rho^2 (a - b T/(1 - b rho))
         const N phi_r = rho_r * rho_r * (C->a_vdw - C->b_vdw * C->T / (1.0 - C->b_vdw * rho_r));
 
-        // 9-point isotropic Laplacian of rho at row r-1 (rho0 drops out)
+        // 9-point isotropic Laplacian of rho at row a-1 (rho0 drops out)
         const N ds_m1 = dsr[iP1], ds_m2 = dsr[i0];
         const N hs_r = from_left(ds_r) + from_right(ds_r);
         const N L_m1 = (4.0 * (hsr[iP1] + ds_r + ds_m2) + hs_r + hsr[i0] - 20.0 * ds_m1) * C->inv_6ds2;
         const N Lrr = from_right(L_m1), Lll = from_left(L_m1);
         const N dL_m1 = Lrr - Lll, sL_m1 = Lrr + Lll;
-        // 9-point isotropic gradient of the Laplacian at row j = r-2
+        // 9-point isotropic gradient of the Laplacian at row o = a-2
         const N g3x = (1.0 / 3.0) * dLr[iP1] + (1.0 / 12.0) * (dL_m1 + dLr[i0]);
         const N g3y = (1.0 / 3.0) * (L_m1 - Lr[i0]) + (1.0 / 12.0) * (sL_m1 - sLr[i0]);
         dsr[iN] = ds_r;
@@ -321,8 +425,8 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         dLr[iN] = dL_m1;
         sLr[iN] = sL_m1;
 
-        // 24-neighbour isotropic gradient of p^i - p^w: row r adds to rows
-        // r-2 .. r+2; ax/ay[(P + d) mod 4] hold the sums of row r-2+d
+        // 24-neighbour isotropic gradient of p^i - p^w: row a adds to rows
+        // a-2 .. a+2; ax/ay[(P + d) mod 4] hold the sums of row a-2+d
         N g5x, g5y;
         {
             using W = G5W<N>;
@@ -345,14 +449,19 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             ay[iN] = -2.0 * B2;
         }
 
-        // --- node quantities of the output row j = r - 2 ------------------------
-        // moments of the output row: u = sum f xi / rho, a2 = sum f (xi xi - I)
+        // --- second step of the split: collision and force on row o ------------
+        // advected row o = a - 2: the ring slot S[i0], or LDS slot (t+1) mod 3
+        auto fo = [&](int k) -> R {
+            if constexpr (PEND_LDS) return pend[((t + 1) % PENDING_ROWS * 16 + k) * WAVE + lane];
+            else return S[i0][k];
+        };
+        // moments of the advected row o: u = sum f xi / rho, a2 = sum f (xi xi - I)
         // (w_k rho_ref drops out of both)
         N jx = 0, jy = 0, axx = 0, axy = 0, ayy = 0;
         static_for<0, 4>([&](auto gc) {
             constexpr int G = decltype(gc)::value;
             constexpr N qx = group_qx(G), qy = group_qy(G);
-            const N d0 = f0[4 * G], d1 = f0[4 * G + 1], d2 = f0[4 * G + 2], d3 = f0[4 * G + 3];
+            const N d0 = fo(4 * G), d1 = fo(4 * G + 1), d2 = fo(4 * G + 2), d3 = fo(4 * G + 3);
             const N see = (d0 + d1) + (d2 + d3);
             const N soe = (d0 - d1) - (d2 - d3);
             const N seo = (d0 + d1) - (d2 + d3);
@@ -394,13 +503,14 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             c03 = dtt * rho_j * uy * (uy * uy * (1.0 / 6.0) + hT) + dt * 0.5 * gy * ayy;
         }
 
-        const bool store_row = t >= 4 && r - 2 < y1;
-        const uint32_t soff = ((uint32_t)(r - 2) * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
+        const bool store_row = t >= 8 && o < y1;
+        const uint32_t soff = ((uint32_t)o * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
         const N dtt = C->dt_tau;
 
-        // collision + force increment w_k P_k - dt/tau d_k of velocity 4G+s,
-        // from the even/odd parts of the polynomial of group G (formed in FP64)
-        auto group_poly = [&](auto gc, N(&poly)[4]) {
+        // f^{n+1}_k = f*_k + (w_k P_k - dt/tau f*_k) for velocity 4G+s, from the
+        // even/odd parts of the polynomial of group G (formed in FP64, added to
+        // f* in the storage precision)
+        static_for<0, 4>([&](auto gc) {
             constexpr int G = decltype(gc)::value;
             constexpr N qx = group_qx(G), qy = group_qy(G), wg = group_w(G);
             const N EE = c00 + c20 * (qx * qx) + c02 * (qy * qy);
@@ -408,91 +518,19 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             const N EO = qy * (c01 + c03 * (qy * qy) + c21 * (qx * qx));
             const N OO = (qx * qy) * c11;
             const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
-            poly[0] = wg * (Pp + Sp) - dtt * (N)f0[4 * G + 0];
-            poly[1] = wg * (Pm - Sm) - dtt * (N)f0[4 * G + 1];
-            poly[2] = wg * (Pp - Sp) - dtt * (N)f0[4 * G + 2];
-            poly[3] = wg * (Pm + Sm) - dtt * (N)f0[4 * G + 3];
-        };
-        // with FP32 storage the 16 increments are rounded to FP32 up front, so
-        // the FP64 coefficients are not held through the advection below
-        constexpr bool EARLY = std::is_same<R, float>::value;
-        R coll_all[16];
-        if constexpr (EARLY) {
-            static_for<0, 4>([&](auto gc) {
-                constexpr int G = decltype(gc)::value;
-                N poly[4];
-                group_poly(gc, poly);
+            const N poly[4] = {wg * (Pp + Sp), wg * (Pm - Sm), wg * (Pp - Sp), wg * (Pm + Sm)};
 #pragma unroll
-                for (int s = 0; s < 4; ++s) coll_all[4 * G + s] = (R)poly[s];
-            });
-        }
-
-        static_for<0, 4>([&](auto gc) {
-            constexpr int G = decltype(gc)::value;
-            N poly[4];
-            if constexpr (!EARLY) group_poly(gc, poly);
-
-            static_for<0, 4>([&](auto sc) {
-                constexpr int K = 4 * G + decltype(sc)::value;
-                constexpr int SX = sign_x(K), SY = sign_y(K), MX = mag_x(K), MY = mag_y(K);
-                const R fj = f0[K];
-                // advective increment A_k(f) - f from upwind differences (exact on
-                // constants): with D1 = f(i - s_x) - f(i) on the output row and on
-                // the row upwind in y, D2 = f(j - s_y) - f(j), the CTU1 part is
-                // a D1 + b D2 + a b (D1(j - s_y) - D1(j)).  D1 of the row that is
-                // reused one row later is carried in cD1.
-                R inc;
-                if constexpr (SY > 0) {
-                    const R rx = fj - from_left(fj);          // R^x at row j
-                    const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
-                    const R D1 = (SX > 0) ? -rx : rxu;
-                    const R D2 = D2m[K];
-                    inc = C->a[MX] * D1 + C->a[MY] * D2 + C->ab[MX][MY] * (cD1[K] - D1);
-                    cD1[K] = D1;
-                    if constexpr (SCHEME == 2) {
-                        // X' at row j and its x-difference; dX of row j-1 is carried
-                        const R X = mc_half(rx, rxu);
-                        const R dXj = from_right(X) - X;
-                        // Y' at row j+1 (ratio with R^y of row j = -D2); Y' of row j is carried
-                        const R Y1 = mc_half(fp1[K] - fj, -D2);
-                        const R dY = Y1 - cY[K];
-                        inc += C->xs1[MX][MY] * dXj + C->xs2[MX][MY] * cdX[K] + C->ys1[MX][MY] * dY
-                             + C->ys2[MX][MY] * upwind_x<SX>(dY);
-                        cdX[K] = dXj;
-                        cY[K] = Y1;
-                    }
-                } else {
-                    const R fjp = fp1[K];
-                    const R rx = fjp - from_left(fjp);        // R^x at row j+1
-                    const R rxu = upwind_x<SX>(rx);
-                    const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row j+1
-                    const R D2 = fjp - fj;
-                    inc = C->a[MX] * cD1[K] + C->a[MY] * D2 + C->ab[MX][MY] * (D1p - cD1[K]);
-                    cD1[K] = D1p;
-                    if constexpr (SCHEME == 2) {
-                        // X' at row j+1 and its x-difference; dX of row j is carried
-                        const R X = mc_half(rx, rxu);
-                        const R dXjp = from_right(X) - X;
-                        // Y' at row j+1 (ratio with R^y of row j+2); Y' of row j is carried
-                        const R Y1 = mc_half(D2, cur[K] - fjp);
-                        const R dY = Y1 - cY[K];
-                        inc += C->xs1[MX][MY] * cdX[K] + C->xs2[MX][MY] * dXjp + C->ys1[MX][MY] * dY
-                             + C->ys2[MX][MY] * upwind_x<SX>(dY);
-                        cdX[K] = dXjp;
-                        cY[K] = Y1;
-                    }
-                }
-                R coll;
-                if constexpr (EARLY) coll = coll_all[K];
-                else coll = (R)poly[decltype(sc)::value];
-                const R fnew = fj + (inc + coll);
+            for (int s = 0; s < 4; ++s) {
+                const int K = 4 * G + s;
+                const R fk = fo(K);
+                const R fnew = fk + (R)(poly[s] - dtt * (N)fk);
                 if (store_row && out_lane) buf_store(fnew, dst, K, soff, pbytes);
-            });
+            }
         });
     };
 
     // scheduling barriers keep the compiler from interleaving consecutive row
-    // bodies (which would raise register pressure past two wavefronts per SIMD)
+    // bodies (which would raise register pressure past the register file)
     for (int t = 0; t < niter4; t += 4) {
         body(std::integral_constant<int, 0>{}, t);
         __builtin_amdgcn_sched_barrier(0);
@@ -516,6 +554,17 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nblocks)
     return x * q + (x < rem ? x : rem) + i;
 }
 
+// dynamic LDS of a step workgroup: step_lds_per_wave<R>() bytes per wavefront
+extern __shared__ __attribute__((aligned(16))) char step_lds[];
+template <typename R>
+__device__ __forceinline__ R* wave_lds()
+{
+    if constexpr (PendingInLds<R>::value)
+        return reinterpret_cast<R*>(step_lds) + (threadIdx.x / WAVE) * (PENDING_ROWS * 16 * WAVE);
+    else
+        return nullptr;
+}
+
 // One wavefront per SIMD with the full register file (up to 512 registers,
 // no spills to memory); the next row is prefetched to cover load latency.
 template <typename R> struct WavesPerEU { static constexpr int value = 1; };
@@ -534,7 +583,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
     const int chunk = wave / nstrips, strip = wave - chunk * nstrips;
     const int y0 = chunk * rows;
     const int y1 = min(y0 + rows, Ly);
-    strip_step<R, SCHEME, REG, WALLS>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1);
+    strip_step<R, SCHEME, REG, WALLS>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1, wave_lds<R>());
 }
 
 template <typename R, int SCHEME, bool REG, bool WALLS>
@@ -551,8 +600,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
     const BatchRun<R> run = runs[it.run];
     const int y0 = it.chunk * run.rows;
     const int y1 = min(y0 + run.rows, run.Ly);
-    strip_step<R, SCHEME, REG, WALLS>(run.f[cur], run.f[cur ^ 1], coefs + it.run,
-                                                              run.Lx, run.Ly, run.plane, it.strip, y0, y1);
+    R* const fa = run.f[0];
+    R* const fb = run.f[1];
+    strip_step<R, SCHEME, REG, WALLS>(cur ? fb : fa, cur ? fa : fb, coefs + it.run,
+                                      run.Lx, run.Ly, run.plane, it.strip, y0, y1, wave_lds<R>());
 }
 
 // ----------------------------------------------------------------------------
@@ -712,8 +763,9 @@ hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int wal
     const int nwaves = rv.nstrips * nchunks;
     const int nblocks = (nwaves + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
-#define LBM_LAUNCH(SC, RG, WL)                                                                              \
-    hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, 0, s, rv.f_in, rv.f_out, rv.coef, rv.Lx, \
+    const size_t lds = wpg * step_lds_per_wave<R>();
+#define LBM_LAUNCH(SC, RG, WL)                                                                                \
+    hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, lds, s, rv.f_in, rv.f_out, rv.coef, rv.Lx, \
                        rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
 #define LBM_LAUNCH_W(SC, RG)          \
     if (walls) LBM_LAUNCH(SC, RG, true); \
@@ -738,8 +790,9 @@ hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coe
     if (nitems <= 0) return hipSuccess;
     const int nblocks = (nitems + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
+    const size_t lds = wpg * step_lds_per_wave<R>();
 #define LBM_LAUNCH(SC, RG, WL) \
-    hipLaunchKernelGGL((batch_step_kernel<R, SC, RG, WL>), grid, block, 0, s, d_runs, d_coefs, d_items, nitems, cur)
+    hipLaunchKernelGGL((batch_step_kernel<R, SC, RG, WL>), grid, block, lds, s, d_runs, d_coefs, d_items, nitems, cur)
 #define LBM_LAUNCH_W(SC, RG)          \
     if (walls) LBM_LAUNCH(SC, RG, true); \
     else LBM_LAUNCH(SC, RG, false)
