@@ -84,8 +84,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
     ap.add_argument("--launch", default=None,
-                    help="fixed launch shape ROWS,WAVES (rows per wavefront, wavefronts per workgroup) instead of "
-                         "the autotuner's")
+                    help="fixed launch shape ROWS,WAVES (rows per wavefront, wavefronts per workgroup) of the FP32 "
+                         "stepper instead of the autotuner's")
+    ap.add_argument("--launch64", default=None, help="the same for the FP64 stepper (WAVES at most 2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -108,7 +109,8 @@ def main():
         torch.cuda.synchronize()
         print("[bench] copy calibration: 5 copies of %d bytes" % (src_t.numel() * 4), file=sys.stderr, flush=True)
         del src_t, dst_t
-    fixed = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    fixed = {"f32": tuple(int(v) for v in args.launch.split(",")) if args.launch else None,
+             "f64": tuple(int(v) for v in args.launch64.split(",")) if args.launch64 else None}
     w = I.large_lattice(args.L)
     rho, ux, uy = w.fields()
     nodes = w.Lx * w.Ly
@@ -118,7 +120,7 @@ def main():
         if name == "f64" and args.fp32_only:
             continue
         p = lbm.Params.from_workload(w, precision=prec)
-        launch = fixed if fixed else (None if args.no_autotune else lbm.autotune(p, steps_per_trial=3))
+        launch = fixed[name] if fixed[name] else (None if args.no_autotune else lbm.autotune(p, steps_per_trial=3))
         run = lbm.Run(p, rho, ux, uy)
         if launch:
             run.set_launch(*launch)
