@@ -36,6 +36,7 @@ class _Params(ctypes.Structure):
         ("bc_y", ctypes.c_int32),
         ("u_wall", ctypes.c_double), ("rho_wall", ctypes.c_double),
         ("limiter", ctypes.c_int32), ("a2_eq", ctypes.c_int32),
+        ("clamp_radius", ctypes.c_double), ("clamp_rho", ctypes.c_double),
     ]
 
 
@@ -58,12 +59,14 @@ class Params:
     rho_wall: float = 1.0
     limiter: int = 1
     a2_eq: int = 0
+    clamp_radius: float = 0.0
+    clamp_rho: float = 1.0
 
     def c(self) -> _Params:
         return _Params(self.Lx, self.Ly, self.ds, self.dt, self.tau, self.T,
                        self.a, self.b, self.kappa, self.scheme, self.regularize,
                        self.bc_y, self.u_wall, self.rho_wall, self.limiter,
-                       self.a2_eq)
+                       self.a2_eq, self.clamp_radius, self.clamp_rho)
 
 
 def _lib():

@@ -32,6 +32,9 @@
  *    order <= 3.
  *  - Shear walls: ghost rows j = -2, -1 hold f^eq(rho_w, (-u_w, 0)) and rows
  *    j = Ly, Ly+1 hold f^eq(rho_w, (+u_w, 0)); x stays periodic.
+ *  - The far-field clamp of Sec. III B is measured from the lattice centre
+ *    ((Lx-1)/2, (Ly-1)/2), the centre of the bubbles, and applies to nodes
+ *    strictly farther than the radius, after each step.
  */
 #include "lbm_oracle.h"
 
@@ -564,6 +567,22 @@ int orc_step_region(const orc_params* p, const double* f_in,
                 out[(size_t)k * nR + r] = fk - dt / p->tau * (fk - feq[k]) + dt * F[k];
             }
         }
+
+    /* 5. far-field density (Sec. III B): outside the circle of radius
+     *    clamp_radius about the lattice centre, f is rescaled by rho_ext / rho */
+    if (p->clamp_radius > 0.0) {
+        const double cx = 0.5 * (p->Lx - 1), cy = 0.5 * (p->Ly - 1);
+        const double r2 = p->clamp_radius * p->clamp_radius;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const double dx = (i0 + x) - cx, dy = (j0 + y) - cy;
+                if (dx * dx + dy * dy <= r2) continue;
+                const size_t r = (size_t)y * nx + x;
+                double rho_n = 0.0;
+                for (int k = 0; k < 16; ++k) rho_n += out[(size_t)k * nR + r];
+                for (int k = 0; k < 16; ++k) out[(size_t)k * nR + r] *= p->clamp_rho / rho_n;
+            }
+    }
 
     free(fE); free(rho); free(ux); free(uy); free(a2);
     free(phi); free(lap); free(gx); free(gy);

@@ -39,6 +39,9 @@ typedef struct {
     double rho_wall;    /* density of the ghost rows                              */
     int32_t limiter;    /* CTU2 only: 1 = MC limiter, 0 = limiter identically 0   */
     int32_t a2_eq;      /* 0 = a2 of f itself (literal), 1 = equilibrium a2       */
+    double clamp_radius; /* > 0: nodes farther than this from the lattice centre
+                            are rescaled to density clamp_rho after the step    */
+    double clamp_rho;
 } orc_params;
 
 /* Velocity set and weights (Table "roots"). */

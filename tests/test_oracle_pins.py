@@ -517,6 +517,26 @@ def test_table_apparentvisco_ctu2_is_tau_minus_half_dt():
             assert abs(r[key] - (r["tau"] + 0.5 * dt)) > 0.9 * dt
 
 
+def test_far_field_clamp():
+    """Sec. III B: after a step, nodes outside the circle of radius R_BC about
+    the centre hold density rho_ext (all f_k scaled by one factor); nodes
+    inside are those of the unclamped step."""
+    p = o.Params(Lx=17, Ly=14, T=0.9, kappa=0.7)
+    f = _random_state(p, 12)
+    free = o.step(p, f)
+    p.clamp_radius, p.clamp_rho = 5.5, 1.31
+    g = o.step(p, f)
+    y, x = np.mgrid[0:p.Ly, 0:p.Lx]
+    out = (x - (p.Lx - 1) / 2) ** 2 + (y - (p.Ly - 1) / 2) ** 2 > 5.5 ** 2
+    assert 0 < out.sum() < out.size
+    np.testing.assert_array_equal(g[:, ~out], free[:, ~out])
+    np.testing.assert_allclose(g.sum(axis=0)[out], 1.31, rtol=1e-14)
+    ratio = g[:, out] / free[:, out]
+    np.testing.assert_allclose(ratio, np.broadcast_to(ratio[0], ratio.shape), rtol=1e-14)
+    part = o.step_region(p, f, 2, 15, 1, 9)
+    np.testing.assert_array_equal(part, g[:, 1:9, 2:15])
+
+
 def test_step_region_matches_whole_step():
     for bc in (0, 1):
         p = o.Params(Lx=11, Ly=9, T=0.9, kappa=0.5, bc_y=bc, u_wall=0.05, rho_wall=1.2, regularize=bc)
