@@ -82,6 +82,11 @@ typedef struct {
                              f^eq(rho_wall, (-u_wall, 0)), rows Ly, Ly+1 hold
                              f^eq(rho_wall, (+u_wall, 0)) (Sec. III C)           */
     double rho_wall;
+    double clamp_radius;  /* > 0: after every step, each node farther than
+                             clamp_radius nodes from ((Lx-1)/2, (Ly-1)/2) has
+                             its f_k rescaled to density clamp_rho (the fixed
+                             far-field density of Sec. III B); <= 0: off      */
+    double clamp_rho;     /* density imposed outside the circle, in (0, 1/b) */
 } lbm_params;
 
 /* FP64 diagnostics of one state (Sec. III C).  Bubble = nodes with
@@ -177,7 +182,7 @@ lbm_status lbm_reduce(lbm_run* run, double rho_threshold, lbm_stats* out, void* 
 
 /* Launch shape: rows of the lattice each wavefront advances (>= 1) and
  * wavefronts per workgroup (1, 2 or 4; at most 2 with FP64 storage, whose
- * kernels use 24 KiB of LDS per wavefront).  LBM_EINVAL otherwise.  Defaults
+ * kernels use 32 KiB of LDS per wavefront).  LBM_EINVAL otherwise.  Defaults
  * come from lbm_autotune or a built-in table. */
 lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per_group);
 lbm_status lbm_get_launch(const lbm_run* run, int32_t* rows_per_wave, int32_t* waves_per_group);

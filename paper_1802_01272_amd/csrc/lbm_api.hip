@@ -62,7 +62,8 @@ lbm_status validate(const lbm_params* p)
     // eight FP64 distribution planes must fit in 4 GiB (32-bit buffer offsets)
     if ((int64_t)p->Lx * (int64_t)p->Ly > (int64_t)1 << 26)
         return fail(LBM_EINVAL, "Lx * Ly must not exceed 2^26 nodes (8192 x 8192)");
-    const double vals[] = {p->ds, p->dt, p->tau, p->T, p->a, p->b, p->kappa, p->rho_ref, p->u_wall, p->rho_wall};
+    const double vals[] = {p->ds, p->dt, p->tau, p->T, p->a, p->b, p->kappa, p->rho_ref, p->u_wall, p->rho_wall,
+                           p->clamp_radius, p->clamp_rho};
     for (double v : vals)
         if (!is_finite_d(v)) return fail(LBM_EINVAL, "parameters must be finite");
     if (p->ds <= 0 || p->dt <= 0) return fail(LBM_EINVAL, "ds and dt must be > 0");
@@ -79,6 +80,10 @@ lbm_status validate(const lbm_params* p)
     if (p->bc_y == LBM_SHEAR_WALLS) {
         if (p->rho_wall <= 0 || (p->b > 0 && p->b * p->rho_wall >= 1.0))
             return fail(LBM_EINVAL, "rho_wall must lie in (0, 1/b)");
+    }
+    if (p->clamp_radius > 0) {
+        if (p->clamp_rho <= 0 || (p->b > 0 && p->b * p->clamp_rho >= 1.0))
+            return fail(LBM_EINVAL, "clamp_rho must lie in (0, 1/b)");
     }
     // CFL condition of the CTU schemes: max_k |xi_k,alpha| dt <= ds
     if (QL * p->dt > p->ds * (1.0 + 1e-12))
@@ -127,6 +132,11 @@ void fill_coef(const lbm_params* p, StepCoef<R>& c)
     c.dt_tau = p->dt / p->tau;
     c.dt = p->dt;
     c.walls = p->bc_y == LBM_SHEAR_WALLS ? 1 : 0;
+    c.clamp = p->clamp_radius > 0 ? 1 : 0;
+    c.clamp_r2 = p->clamp_radius > 0 ? p->clamp_radius * p->clamp_radius : 0.0;
+    c.clamp_cx = 0.5 * (p->Lx - 1);
+    c.clamp_cy = 0.5 * (p->Ly - 1);
+    c.clamp_rho = p->clamp_rho;
 }
 
 size_t storage_bytes(const lbm_params* p) { return p->precision == LBM_FP32_DEV ? 4 : 8; }

@@ -37,10 +37,11 @@ constexpr int WAVE = 64;
 constexpr int HALO = 4;
 constexpr int STRIP = WAVE - 2 * HALO;
 
-// The step kernels hold the advected rows that wait for their collision (three
-// rows of 16 values per lane) in LDS for FP64 storage, in registers for FP32.
+// The step kernels hold the advected rows that wait for their collision (a
+// ring of four rows of 16 values per lane, indexed by the row phase) in LDS
+// for FP64 storage, in registers for FP32.
 template <typename R> struct PendingInLds { static constexpr bool value = sizeof(R) == 8; };
-constexpr int PENDING_ROWS = 3;
+constexpr int PENDING_ROWS = 4;
 template <typename R>
 constexpr size_t step_lds_per_wave()
 {
@@ -74,8 +75,11 @@ struct StepCoef {
     double dt_tau;      // dt / tau
     double dt;
     double ghost_rho_lo, ghost_rho_hi;  // density of the ghost rows (sum of their f)
+    // far-field clamp: nodes with (i - cx)^2 + (j - cy)^2 > r2 are rescaled to
+    // density clamp_rho after the step
+    double clamp_r2, clamp_cx, clamp_cy, clamp_rho;
     int32_t walls;
-    int32_t pad_;
+    int32_t clamp;
 };
 
 // magnitude class of the x / y component of velocity k

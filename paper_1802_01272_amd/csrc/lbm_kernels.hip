@@ -222,9 +222,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     // a, a+1; S[P] receives the advected row a, and S[P+2], S[P+3] hold the
     // advected rows a-2, a-1.  Roles move by index, never by copying.  Row
     // r+1 is loaded during phase P into B[P+1] once row a-1 has been used.
-    // With PEND_LDS the advected rows wait instead in three LDS slots of this
-    // wavefront (slot t mod 3 receives row a; each lane reads back only what
-    // it wrote, so no barrier is needed).
+    // With PEND_LDS the advected rows wait instead in four LDS slots of this
+    // wavefront, indexed like S (each lane reads back only what it wrote, so
+    // no barrier is needed).
     R B[4][16];
     R S[4][16];
     // carries per velocity: the upwind x-difference D1 of the row the CTU1
@@ -404,7 +404,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         }
         if constexpr (PEND_LDS) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) pend[((t % PENDING_ROWS) * 16 + k) * WAVE + lane] = fs[k];
+            for (int k = 0; k < 16; ++k) pend[(iN * 16 + k) * WAVE + lane] = fs[k];
         }
         const N rho_r = C->rho0 + ds_r;
         // p^i - p^w = rho T - rho T/(1 - b rho) + a rho^2 = rho^2 (a - b T/(1 - b rho))
@@ -450,9 +450,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         }
 
         // --- second step of the split: collision and force on row o ------------
-        // advected row o = a - 2: the ring slot S[i0], or LDS slot (t+1) mod 3
+        // advected row o = a - 2: ring slot i0, in registers or in LDS
         auto fo = [&](int k) -> R {
-            if constexpr (PEND_LDS) return pend[((t + 1) % PENDING_ROWS * 16 + k) * WAVE + lane];
+            if constexpr (PEND_LDS) return pend[(i0 * 16 + k) * WAVE + lane];
             else return S[i0][k];
         };
         // moments of the advected row o: u = sum f xi / rho, a2 = sum f (xi xi - I)
@@ -503,13 +503,27 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             c03 = dtt * rho_j * uy * (uy * uy * (1.0 / 6.0) + hT) + dt * 0.5 * gy * ayy;
         }
 
+        // far-field clamp (Sec. III B): outside the circle the new state is
+        // scaled by s = rho_ext / rho^{n+1}, where rho^{n+1} = rho* because the
+        // collision and the force conserve mass.  With A = s (1 - dt/tau),
+        // f^{n+1}_k = A f*_k + w_k s P_k, and in deviation storage
+        // d^{n+1}_k = A d*_k + w_k (s P_k + (s - 1) rho_ref).
+        N s = 1.0;
+        if (C->clamp) {
+            const N dx = (N)col - C->clamp_cx, dy = (N)o - C->clamp_cy;
+            if (dx * dx + dy * dy > C->clamp_r2) s = C->clamp_rho * inv_rho;
+        }
+        const N A = s * (1.0 - C->dt_tau);
+        c00 = s * c00 + (s - 1.0) * C->rho0;
+        c10 *= s; c01 *= s; c20 *= s; c02 *= s; c11 *= s;
+        c30 *= s; c21 *= s; c12 *= s; c03 *= s;
+
         const bool store_row = t >= 8 && o < y1;
         const uint32_t soff = ((uint32_t)o * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
-        const N dtt = C->dt_tau;
 
-        // f^{n+1}_k = f*_k + (w_k P_k - dt/tau f*_k) for velocity 4G+s, from the
-        // even/odd parts of the polynomial of group G (formed in FP64, added to
-        // f* in the storage precision)
+        // f^{n+1}_k = A f*_k + w_k P_k for velocity 4G+s, from the even/odd
+        // parts of the polynomial of group G, in FP64 with one rounding to
+        // the storage precision
         static_for<0, 4>([&](auto gc) {
             constexpr int G = decltype(gc)::value;
             constexpr N qx = group_qx(G), qy = group_qy(G), wg = group_w(G);
@@ -520,10 +534,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
             const N poly[4] = {wg * (Pp + Sp), wg * (Pm - Sm), wg * (Pp - Sp), wg * (Pm + Sm)};
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int K = 4 * G + s;
-                const R fk = fo(K);
-                const R fnew = fk + (R)(poly[s] - dtt * (N)fk);
+            for (int sv = 0; sv < 4; ++sv) {
+                const int K = 4 * G + sv;
+                const R fnew = (R)(A * (N)fo(K) + poly[sv]);
                 if (store_row && out_lane) buf_store(fnew, dst, K, soff, pbytes);
             }
         });

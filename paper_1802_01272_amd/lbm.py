@@ -40,6 +40,7 @@ class CParams(ctypes.Structure):
         ("rho_ref", ctypes.c_double),
         ("bc_y", ctypes.c_int32),
         ("u_wall", ctypes.c_double), ("rho_wall", ctypes.c_double),
+        ("clamp_radius", ctypes.c_double), ("clamp_rho", ctypes.c_double),
     ]
 
 
@@ -69,6 +70,8 @@ class Params:
     bc_y: int = PERIODIC
     u_wall: float = 0.0
     rho_wall: float = 1.0
+    clamp_radius: float = 0.0
+    clamp_rho: float = 1.0
 
     def c(self) -> CParams:
         return CParams(*[getattr(self, f.name) for f in fields(self)])

@@ -8,7 +8,7 @@ from paper_1802_01272_amd import lbm
 def oracle_params(p: "lbm.Params") -> o.Params:
     return o.Params(Lx=p.Lx, Ly=p.Ly, ds=p.ds, dt=p.dt, tau=p.tau, T=p.T, a=p.a, b=p.b, kappa=p.kappa,
                     scheme=p.scheme, regularize=p.regularize, bc_y=p.bc_y, u_wall=p.u_wall,
-                    rho_wall=p.rho_wall)
+                    rho_wall=p.rho_wall, clamp_radius=p.clamp_radius, clamp_rho=p.clamp_rho)
 
 
 def random_state(p: "lbm.Params", seed: int, amp: float = 0.03, rho_mean: float = 1.2, rho_amp: float = 0.15):

@@ -108,6 +108,38 @@ def test_one_step_fp32dev(Lx, Ly, scheme, reg, bc):
     assert rel_err(got, ref) < F32_STEP
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_far_field_clamp_one_step(precision, scheme):
+    """Density clamp outside the circle of radius R_BC (Sec. III B)."""
+    p = make_params(90, 70, scheme, 0, 0, precision=precision, clamp_radius=24.5, clamp_rho=1.31)
+    f = random_state(p, 90 + scheme)
+    run = lbm.Run(p, 1.0, 0.0, 0.0)
+    run.set_f(f)
+    f_stored = run.get_f()
+    run.step(1)
+    got = run.get_f()
+    run.close()
+    ref = o.step(oracle_params(p), f_stored)
+    assert rel_err(got, ref) < (F64_STEP if precision == 0 else F32_STEP)
+    y, x = np.mgrid[0:70, 0:90]
+    out = (x - 44.5) ** 2 + (y - 34.5) ** 2 > 24.5 ** 2
+    np.testing.assert_allclose(got.sum(axis=0)[out], 1.31, rtol=1e-13 if precision == 0 else 1e-6)
+
+
+def test_bubble_with_clamp_fp64_many_steps():
+    """A vapour bubble in a clamped superheated liquid, 400 steps, FP64."""
+    w = I.quiescent_bubble(80, radius=10.0)
+    rho, ux, uy = w.fields()
+    p = lbm.Params.from_workload(w, clamp_radius=30.0, clamp_rho=w.rho_ext)
+    run = lbm.Run(p, rho, ux, uy)
+    run.step(400)
+    got = run.get_f()
+    op = oracle_params(p)
+    ref = o.run(op, o.init(op, rho, ux, uy), 400)
+    assert rel_err(got, ref) < 1e-10
+
+
 @pytest.mark.parametrize("Lx,Ly", [(1, 1), (1, 6), (2, 3), (5, 1), (55, 4), (56, 2), (57, 3), (63, 5), (64, 3),
                                    (65, 7), (111, 2), (112, 5), (113, 1), (200, 1)])
 @pytest.mark.parametrize("bc", [0, 1])
@@ -135,7 +167,7 @@ def test_launch_shape_does_not_change_results(precision, launch):
 
 
 def test_fp64_rejects_four_waves_per_group():
-    """FP64 kernels hold 24 KiB of LDS per wavefront: four per workgroup are
+    """FP64 kernels hold 32 KiB of LDS per wavefront: four per workgroup are
     refused with LBM_EINVAL and the previous shape is kept."""
     run = lbm.Run(make_params(40, 20), 1.0, 0.0, 0.0)
     run.set_launch(16, 2)
