@@ -104,6 +104,7 @@ void fill_coef(const lbm_params* p, StepCoef<R>& c)
         for (int my = 0; my < 2; ++my) {
             const double ay = nu * q[my], k2y = q[my] * (1 - ay);
             c.ab[mx][my] = (R)(ax * ay);
+            c.amab[mx][my] = (R)(ax - ax * ay);
             c.xs1[mx][my] = (R)(-nu * (1 - ay) * k2x);
             c.xs2[mx][my] = (R)(-nu * ay * k2x);
             c.ys1[mx][my] = (R)(-nu * (1 - ax) * k2y);

@@ -57,6 +57,7 @@ struct StepCoef {
     // of a velocity component (0: |xi| = QS, 1: |xi| = QL); nu = dt/ds
     R a[2];        // nu |xi|                            (CTU1 increment weights)
     R ab[2][2];    // a[mx] * a[my]
+    R amab[2][2];  // a[mx] - a[mx] * a[my]
     // CTU2: the limited corrections are kept unscaled, X' = S^x / k2[mx] and
     // Y' = S^y / k2[my] with k2 = |xi| (1 - nu |xi|); the scales are folded
     // into the blend weights of their differences, indexed [mx][my]:

@@ -124,6 +124,17 @@ __device__ __forceinline__ void buf_store(double v, const FieldRsrc& f, int k, u
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0);
 }
 
+// 1/x for x of order one (densities, 1 - b rho): hardware reciprocal refined
+// by two Newton steps, within an ulp or two of the correctly rounded quotient
+__device__ __forceinline__ double recip(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
 // compile-time choice between two arrays of one type
 template <bool FIRST, typename T>
 __device__ __forceinline__ T& pick(T& a, T& b)
@@ -252,7 +263,10 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         for (int k = 0; k < 16; ++k) load_one(k, voff, ghost, B[0][k]);
     }
 
-    auto body = [&](auto ph, const int t) {
+    // COLL = false: the first eight rows of the march only fill the rings
+    // (advection, density, stencil sums); nothing is collided or stored.
+    auto body = [&](auto ph, auto coll, const int t) {
+        constexpr bool COLL = decltype(coll)::value;
         constexpr int P = decltype(ph)::value;
         constexpr int iN = P, iM1 = (P + 1) & 3, i0 = (P + 2) & 3, iP1 = (P + 3) & 3;
         R(&cur)[16] = B[iN];
@@ -290,7 +304,8 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             // advective increment A_k(f) - f from upwind differences (exact on
             // constants): with D1 = f(i - s_x) - f(i) on row a and on the row
             // upwind in y, D2 = f(a - s_y) - f(a), the CTU1 part is
-            // a D1 + b D2 + a b (D1(a - s_y) - D1(a)).  D1 of the row that is
+            // a D1 + b D2 + a b (D1(a - s_y) - D1(a)), evaluated as
+            // (a - a b) D1(a) + b D2 + a b D1(a - s_y).  D1 of the row that is
             // reused one row later is carried in cD1.
             R inc;
             if constexpr (SY > 0) {
@@ -298,7 +313,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
                 const R D1 = (SX > 0) ? -rx : rxu;
                 const R D2 = D2m[K];
-                inc = C->a[MX] * D1 + C->a[MY] * D2 + C->ab[MX][MY] * (cD1[K] - D1);
+                inc = C->amab[MX][MY] * D1 + C->a[MY] * D2 + C->ab[MX][MY] * cD1[K];
                 cD1[K] = D1;
                 if constexpr (SCHEME == 2) {
                     // X' at row a and its x-difference; dX of row a-1 is carried
@@ -318,7 +333,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R rxu = upwind_x<SX>(rx);
                 const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row a+1
                 const R D2 = fjp - fj;
-                inc = C->a[MX] * cD1[K] + C->a[MY] * D2 + C->ab[MX][MY] * (D1p - cD1[K]);
+                inc = C->amab[MX][MY] * cD1[K] + C->a[MY] * D2 + C->ab[MX][MY] * D1p;
                 cD1[K] = D1p;
                 if constexpr (SCHEME == 2) {
                     // X' at row a+1 and its x-difference; dX of row a is carried
@@ -408,7 +423,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         }
         const N rho_r = C->rho0 + ds_r;
         // p^i - p^w = rho T - rho T/(1 - b rho) + a rho^2 = rho^2 (a - b T/(1 - b rho))
-        const N phi_r = rho_r * rho_r * (C->a_vdw - C->b_vdw * C->T / (1.0 - C->b_vdw * rho_r));
+        const N phi_r = rho_r * rho_r * (C->a_vdw - C->b_vdw * C->T * recip(1.0 - C->b_vdw * rho_r));
 
         // 9-point isotropic Laplacian of rho at row a-1 (rho0 drops out)
         const N ds_m1 = dsr[iP1], ds_m2 = dsr[i0];
@@ -449,109 +464,131 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             ay[iN] = -2.0 * B2;
         }
 
-        // --- second step of the split: collision and force on row o ------------
-        // advected row o = a - 2: ring slot i0, in registers or in LDS
-        auto fo = [&](int k) -> R {
-            if constexpr (PEND_LDS) return pend[(i0 * 16 + k) * WAVE + lane];
-            else return S[i0][k];
-        };
-        // moments of the advected row o: u = sum f xi / rho, a2 = sum f (xi xi - I)
-        // (w_k rho_ref drops out of both)
-        N jx = 0, jy = 0, axx = 0, axy = 0, ayy = 0;
-        static_for<0, 4>([&](auto gc) {
-            constexpr int G = decltype(gc)::value;
-            constexpr N qx = group_qx(G), qy = group_qy(G);
-            const N d0 = fo(4 * G), d1 = fo(4 * G + 1), d2 = fo(4 * G + 2), d3 = fo(4 * G + 3);
-            const N see = (d0 + d1) + (d2 + d3);
-            const N soe = (d0 - d1) - (d2 - d3);
-            const N seo = (d0 + d1) - (d2 + d3);
-            const N soo = (d0 - d1) + (d2 - d3);
-            jx += qx * soe;
-            jy += qy * seo;
-            axx += (qx * qx - 1.0) * see;
-            ayy += (qy * qy - 1.0) * see;
-            axy += (qx * qy) * soo;
-        });
+        if constexpr (COLL) {
+            // --- second step of the split: collision and force on row o ------------
+            // advected row o = a - 2: ring slot i0, in registers or in LDS
+            auto fo = [&](int k) -> R {
+                if constexpr (PEND_LDS) return pend[(i0 * 16 + k) * WAVE + lane];
+                else return S[i0][k];
+            };
+            // moments of the advected row o: u = sum f xi / rho, a2 = sum f (xi xi - I)
+            // (w_k rho_ref drops out of both)
+            N jx = 0, jy = 0, axx = 0, axy = 0, ayy = 0;
+            static_for<0, 4>([&](auto gc) {
+                constexpr int G = decltype(gc)::value;
+                constexpr N qx = group_qx(G), qy = group_qy(G);
+                const N d0 = fo(4 * G), d1 = fo(4 * G + 1), d2 = fo(4 * G + 2), d3 = fo(4 * G + 3);
+                const N see = (d0 + d1) + (d2 + d3);
+                const N soe = (d0 - d1) - (d2 - d3);
+                const N seo = (d0 + d1) - (d2 + d3);
+                const N soo = (d0 - d1) + (d2 - d3);
+                jx += qx * soe;
+                jy += qy * seo;
+                axx += (qx * qx - 1.0) * see;
+                ayy += (qy * qy - 1.0) * see;
+                axy += (qx * qy) * soo;
+            });
 
-        const N ds_j = ds_m2;
-        const N rho_j = C->rho0 + ds_j;
-        const N inv_rho = 1.0 / rho_j;
-        const N gx = g5x * C->inv_ds * inv_rho + C->kappa_ds * g3x;
-        const N gy = g5y * C->inv_ds * inv_rho + C->kappa_ds * g3y;
-        const N ux = jx * inv_rho, uy = jy * inv_rho;
+            const N ds_j = ds_m2;
+            const N rho_j = C->rho0 + ds_j;
+            const N inv_rho = recip(rho_j);
+            const N gx = g5x * C->inv_ds * inv_rho + C->kappa_ds * g3x;
+            const N gy = g5y * C->inv_ds * inv_rho + C->kappa_ds * g3y;
+            const N ux = jx * inv_rho, uy = jy * inv_rho;
 
-        // collision + force as dt/tau f^eq_k + dt F_k = w_k sum_mn c_mn xi_x^m xi_y^n;
-        // in deviation storage c00 also absorbs -dt/tau rho_ref
-        N c00, c10, c01, c20, c02, c11, c30, c21, c12, c03;
-        {
-            const N dtt = C->dt_tau, dt = C->dt, T1 = C->Tm1;
-            const N hu = 0.5 * (ux * ux + uy * uy);
-            const N hT = 0.5 * T1;
-            const N tr = axx + ayy;
-            const N vx = axx * gx + axy * gy, vy = axy * gx + ayy * gy;
-            const N gu = gx * ux + gy * uy;
-            const N lin = 1.0 - hu - 2.0 * T1;
-            c00 = dtt * (ds_j - rho_j * (hu + T1)) - dt * rho_j * gu;
-            c10 = dtt * rho_j * ux * lin + dt * (rho_j * gx - 0.5 * gx * tr - vx);
-            c01 = dtt * rho_j * uy * lin + dt * (rho_j * gy - 0.5 * gy * tr - vy);
-            c20 = dtt * rho_j * (0.5 * ux * ux + hT) + dt * rho_j * gx * ux;
-            c02 = dtt * rho_j * (0.5 * uy * uy + hT) + dt * rho_j * gy * uy;
-            c11 = dtt * rho_j * ux * uy + dt * rho_j * (gx * uy + gy * ux);
-            c30 = dtt * rho_j * ux * (ux * ux * (1.0 / 6.0) + hT) + dt * 0.5 * gx * axx;
-            c21 = dtt * rho_j * uy * (0.5 * ux * ux + hT) + dt * (gx * axy + 0.5 * gy * axx);
-            c12 = dtt * rho_j * ux * (0.5 * uy * uy + hT) + dt * (0.5 * gx * ayy + gy * axy);
-            c03 = dtt * rho_j * uy * (uy * uy * (1.0 / 6.0) + hT) + dt * 0.5 * gy * ayy;
-        }
-
-        // far-field clamp (Sec. III B): outside the circle the new state is
-        // scaled by s = rho_ext / rho^{n+1}, where rho^{n+1} = rho* because the
-        // collision and the force conserve mass.  With A = s (1 - dt/tau),
-        // f^{n+1}_k = A f*_k + w_k s P_k, and in deviation storage
-        // d^{n+1}_k = A d*_k + w_k (s P_k + (s - 1) rho_ref).
-        N s = 1.0;
-        if (C->clamp) {
-            const N dx = (N)col - C->clamp_cx, dy = (N)o - C->clamp_cy;
-            if (dx * dx + dy * dy > C->clamp_r2) s = C->clamp_rho * inv_rho;
-        }
-        const N A = s * (1.0 - C->dt_tau);
-        c00 = s * c00 + (s - 1.0) * C->rho0;
-        c10 *= s; c01 *= s; c20 *= s; c02 *= s; c11 *= s;
-        c30 *= s; c21 *= s; c12 *= s; c03 *= s;
-
-        const bool store_row = t >= 8 && o < y1;
-        const uint32_t soff = ((uint32_t)o * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
-
-        // f^{n+1}_k = A f*_k + w_k P_k for velocity 4G+s, from the even/odd
-        // parts of the polynomial of group G, in FP64 with one rounding to
-        // the storage precision
-        static_for<0, 4>([&](auto gc) {
-            constexpr int G = decltype(gc)::value;
-            constexpr N qx = group_qx(G), qy = group_qy(G), wg = group_w(G);
-            const N EE = c00 + c20 * (qx * qx) + c02 * (qy * qy);
-            const N OE = qx * (c10 + c30 * (qx * qx) + c12 * (qy * qy));
-            const N EO = qy * (c01 + c03 * (qy * qy) + c21 * (qx * qx));
-            const N OO = (qx * qy) * c11;
-            const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
-            const N poly[4] = {wg * (Pp + Sp), wg * (Pm - Sm), wg * (Pp - Sp), wg * (Pm + Sm)};
-#pragma unroll
-            for (int sv = 0; sv < 4; ++sv) {
-                const int K = 4 * G + sv;
-                const R fnew = (R)(A * (N)fo(K) + poly[sv]);
-                if (store_row && out_lane) buf_store(fnew, dst, K, soff, pbytes);
+            // collision + force as dt/tau f^eq_k + dt F_k = w_k sum_mn c_mn xi_x^m xi_y^n;
+            // in deviation storage c00 also absorbs -dt/tau rho_ref
+            N c00, c10, c01, c20, c02, c11, c30, c21, c12, c03;
+            {
+                const N dtt = C->dt_tau, dt = C->dt, T1 = C->Tm1;
+                const N hu = 0.5 * (ux * ux + uy * uy);
+                const N hT = 0.5 * T1;
+                const N tr = axx + ayy;
+                const N vx = axx * gx + axy * gy, vy = axy * gx + ayy * gy;
+                const N gu = gx * ux + gy * uy;
+                const N lin = 1.0 - hu - 2.0 * T1;
+                c00 = dtt * (ds_j - rho_j * (hu + T1)) - dt * rho_j * gu;
+                c10 = dtt * rho_j * ux * lin + dt * (rho_j * gx - 0.5 * gx * tr - vx);
+                c01 = dtt * rho_j * uy * lin + dt * (rho_j * gy - 0.5 * gy * tr - vy);
+                c20 = dtt * rho_j * (0.5 * ux * ux + hT) + dt * rho_j * gx * ux;
+                c02 = dtt * rho_j * (0.5 * uy * uy + hT) + dt * rho_j * gy * uy;
+                c11 = dtt * rho_j * ux * uy + dt * rho_j * (gx * uy + gy * ux);
+                c30 = dtt * rho_j * ux * (ux * ux * (1.0 / 6.0) + hT) + dt * 0.5 * gx * axx;
+                c21 = dtt * rho_j * uy * (0.5 * ux * ux + hT) + dt * (gx * axy + 0.5 * gy * axx);
+                c12 = dtt * rho_j * ux * (0.5 * uy * uy + hT) + dt * (0.5 * gx * ayy + gy * axy);
+                c03 = dtt * rho_j * uy * (uy * uy * (1.0 / 6.0) + hT) + dt * 0.5 * gy * ayy;
             }
-        });
+
+            // far-field clamp (Sec. III B): outside the circle the new state is
+            // scaled by s = rho_ext / rho^{n+1}, where rho^{n+1} = rho* because the
+            // collision and the force conserve mass.  With A = s (1 - dt/tau),
+            // f^{n+1}_k = A f*_k + w_k s P_k, and in deviation storage
+            // d^{n+1}_k = A d*_k + w_k (s P_k + (s - 1) rho_ref).
+            N s = 1.0;
+            if (C->clamp) {
+                const N dx = (N)col - C->clamp_cx, dy = (N)o - C->clamp_cy;
+                if (dx * dx + dy * dy > C->clamp_r2) s = C->clamp_rho * inv_rho;
+            }
+            const N A = s * (1.0 - C->dt_tau);
+            c00 = s * c00 + (s - 1.0) * C->rho0;
+            c10 *= s; c01 *= s; c20 *= s; c02 *= s; c11 *= s;
+            c30 *= s; c21 *= s; c12 *= s; c03 *= s;
+
+            const bool store_row = t >= 8 && o < y1;
+            const uint32_t soff = ((uint32_t)o * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
+
+            // f^{n+1}_k = A f*_k + w_k P_k for velocity 4G+s, from the even/odd
+            // parts of the polynomial of group G, in FP64 with one rounding to
+            // the storage precision
+            static_for<0, 4>([&](auto gc) {
+                constexpr int G = decltype(gc)::value;
+                constexpr N qx = group_qx(G), qy = group_qy(G), wg = group_w(G);
+                const N EE = c00 + c20 * (qx * qx) + c02 * (qy * qy);
+                const N OE = qx * (c10 + c30 * (qx * qx) + c12 * (qy * qy));
+                const N EO = qy * (c01 + c03 * (qy * qy) + c21 * (qx * qx));
+                const N OO = (qx * qy) * c11;
+                const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
+                const N poly[4] = {wg * (Pp + Sp), wg * (Pm - Sm), wg * (Pp - Sp), wg * (Pm + Sm)};
+    #pragma unroll
+                for (int sv = 0; sv < 4; ++sv) {
+                    const int K = 4 * G + sv;
+                    const R fnew = (R)(A * (N)fo(K) + poly[sv]);
+                    if (store_row && out_lane) buf_store(fnew, dst, K, soff, pbytes);
+                }
+            });
+        }
     };
 
     // scheduling barriers keep the compiler from interleaving consecutive row
     // bodies (which would raise register pressure past the register file)
-    for (int t = 0; t < niter4; t += 4) {
-        body(std::integral_constant<int, 0>{}, t);
+    using Z = std::integral_constant<bool, false>;
+    using O = std::integral_constant<bool, true>;
+    // FP32: the eight warm-up rows run a body without the collision; FP64
+    // keeps one body for all rows (a second copy of the larger FP64 body
+    // costs more in instruction fetch than the collisions it skips).
+    constexpr bool PEEL = sizeof(R) == 4;
+    int t0 = 0;
+    if constexpr (PEEL) {
+        t0 = 8;
+        for (int t = 0; t < 8; t += 4) {
+            body(std::integral_constant<int, 0>{}, Z{}, t);
+            __builtin_amdgcn_sched_barrier(0);
+            body(std::integral_constant<int, 1>{}, Z{}, t + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            body(std::integral_constant<int, 2>{}, Z{}, t + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            body(std::integral_constant<int, 3>{}, Z{}, t + 3);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    for (int t = t0; t < niter4; t += 4) {
+        body(std::integral_constant<int, 0>{}, O{}, t);
         __builtin_amdgcn_sched_barrier(0);
-        body(std::integral_constant<int, 1>{}, t + 1);
+        body(std::integral_constant<int, 1>{}, O{}, t + 1);
         __builtin_amdgcn_sched_barrier(0);
-        body(std::integral_constant<int, 2>{}, t + 2);
+        body(std::integral_constant<int, 2>{}, O{}, t + 2);
         __builtin_amdgcn_sched_barrier(0);
-        body(std::integral_constant<int, 3>{}, t + 3);
+        body(std::integral_constant<int, 3>{}, O{}, t + 3);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
