@@ -74,6 +74,58 @@ def cpu_baseline(workload, rho, ux, uy, budget_s=12.0, rows=256, max_steps=20):
             "sample": "%d x %d band of the workload's initial state (periodic), %d steps, FP64" % (p.Lx, rows, steps)}
 
 
+def timed_steps(torch, fn, steps):
+    """Device milliseconds of fn(steps), HIP events on torch's current stream
+    (the stream the library launches on)."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def batched_sweep(args, torch, I, lbm, graph_steps=20):
+    """Aggregate MLUPS of the 32-run sweep (lattice edges 256..1536, T/T_c in
+    [0.85, 0.97], shear rates 0, 1e-5, 1e-4, FP32 deviation storage): one
+    batched launch per step, replayed from a HIP graph, rows per wavefront
+    from the batch autotuner; against the same runs stepped one after another,
+    each with its own autotuned launch shape."""
+    sweep = I.batched_sweep(32, seed=5)
+    params = [lbm.Params.from_workload(w, precision=lbm.FP32_DEV) for w in sweep]
+    fields = [w.fields() for w in sweep]
+    nodes = sum(w.Lx * w.Ly for w in sweep)
+    steps = args.steps
+    batch = lbm.Batch(params, fields)
+    rows = batch.autotune(2)
+    batch.step(args.warmup, graph_steps=graph_steps)
+    ms_batch = timed_steps(torch, lambda n: batch.step(n, graph_steps=graph_steps), steps)
+    batch.close()
+    del batch
+    torch.cuda.empty_cache()
+    ms_seq = 0.0
+    for p, (rho, ux, uy) in zip(params, fields):
+        launch = lbm.autotune(p, steps_per_trial=2)
+        run = lbm.Run(p, rho, ux, uy)
+        run.set_launch(*launch)
+        run.step(args.warmup)
+        ms_seq += timed_steps(torch, run.step, steps)
+        run.close()
+    value = nodes * steps / (ms_batch * 1e-3) / 1e6
+    seq = nodes * steps / (ms_seq * 1e-3) / 1e6
+    return {"metric": "aggregate MLUPS, batched sweep vs the same runs sequentially", "value": round(value, 1),
+            "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+            "ms_per_step": round(ms_batch / steps, 5), "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "batched_sweep_32", "runs": len(sweep), "nodes": nodes,
+                       "edges": sorted({w.Lx for w in sweep}), "rows_per_wave": rows, "graph_steps": graph_steps,
+                       "storage": "FP32 f - w rho_ref"},
+            "sequential": {"value": round(seq, 1), "ms_per_step": round(ms_seq / steps, 5)},
+            "speedup_batched_over_sequential": round(ms_seq / ms_batch, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +139,9 @@ def main():
                     help="fixed launch shape ROWS,WAVES (rows per wavefront, wavefronts per workgroup) of the FP32 "
                          "stepper instead of the autotuner's")
     ap.add_argument("--launch64", default=None, help="the same for the FP64 stepper (WAVES at most 2)")
+    ap.add_argument("--batched", action="store_true",
+                    help="instead of the 6144^2 lattice: the 32-run sweep of uneven lattices in one batched, "
+                         "graph-captured launch per step against the same runs stepped one after another")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -101,6 +156,9 @@ def main():
     from paper_1802_01272_amd import lbm
 
     torch.cuda.set_device(0)
+    if args.batched:
+        print(json.dumps(batched_sweep(args, torch, I, lbm)), flush=True)
+        return
     if args.copy_calibration:
         src_t = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst_t = torch.empty_like(src_t)

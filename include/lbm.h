@@ -214,6 +214,16 @@ lbm_status lbm_batch_init(int32_t n, const lbm_params* params, void* d_ws, size_
  * one HIP graph on first use and replays it; 0 launches directly.  async. */
 lbm_status lbm_batch_step(lbm_batch* batch, int64_t nsteps, int32_t graph_steps, void* stream);
 
+/* Rows of each run that one wavefront advances (>= 1) for every run of the
+ * batch; rebuilds the work list and drops a captured graph.  sync. */
+lbm_status lbm_batch_set_launch(lbm_batch* batch, int32_t rows_per_wave, void* stream);
+
+/* Time candidate rows-per-wavefront values on the batch itself and keep the
+ * fastest.  The trials advance every run: by (steps_per_trial + 1) steps per
+ * candidate (8 candidates).  sync. */
+lbm_status lbm_batch_autotune(lbm_batch* batch, int32_t steps_per_trial, void* stream,
+                              int32_t* rows_per_wave);
+
 /* Borrowed handle of run r (valid while the batch lives) for lbm_moments,
  * lbm_get_f, lbm_set_f and lbm_reduce; lbm_step on it is rejected. */
 lbm_run* lbm_batch_run(lbm_batch* batch, int32_t r);

@@ -880,6 +880,62 @@ lbm_run* lbm_batch_run(lbm_batch* b, int32_t r)
     return &b->runs[r];
 }
 
+lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t rows_per_wave, void* stream)
+{
+    if (!b) return fail(LBM_EINVAL, "null batch");
+    if (rows_per_wave < 1) return fail(LBM_EINVAL, "rows_per_wave must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamSynchronize(s), "batch set launch");
+    for (auto& r : b->runs) r.launch.rows_per_wave = rows_per_wave;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->graph_steps = 0;
+    }
+    char* base = static_cast<char*>(b->d_runs);
+    return (b->precision == LBM_FP32_DEV) ? batch_tables<float>(b, base, s) : batch_tables<double>(b, base, s);
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps_per_trial, void* stream, int32_t* rows_per_wave)
+{
+    if (!b || !rows_per_wave) return fail(LBM_EINVAL, "null argument");
+    if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int rows_c[] = {16, 32, 48, 64, 96, 128, 192, 256};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "batch autotune");
+    HIP_TRY(hipEventCreate(&e1), "batch autotune");
+    double best = 1e300;
+    int best_rows = rows_c[0];
+    lbm_status st = LBM_OK;
+    for (int rows : rows_c) {
+        st = lbm_batch_set_launch(b, rows, stream);
+        if (st != LBM_OK) break;
+        st = lbm_batch_step(b, 1, 0, stream);
+        if (st != LBM_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(LBM_EDEVICE, "batch autotune event"); break; }
+        st = lbm_batch_step(b, steps_per_trial, 0, stream);
+        if (st != LBM_OK) break;
+        float ms = 0;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess
+            || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(LBM_EDEVICE, "batch autotune timing");
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            best_rows = rows;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LBM_OK) return st;
+    *rows_per_wave = best_rows;
+    return lbm_batch_set_launch(b, best_rows, stream);
+}
+
 void lbm_batch_destroy(lbm_batch* b)
 {
     if (!b) return;

@@ -127,6 +127,8 @@ def _load():
         "lbm_batch_init": ([ctypes.c_int32, P, vp, ctypes.c_size_t, vp, ctypes.POINTER(D), ctypes.POINTER(D),
                             ctypes.POINTER(D), ctypes.POINTER(vp)], st),
         "lbm_batch_step": ([vp, ctypes.c_int64, ctypes.c_int32, vp], st),
+        "lbm_batch_set_launch": ([vp, ctypes.c_int32, vp], st),
+        "lbm_batch_autotune": ([vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)], st),
         "lbm_batch_run": ([vp, ctypes.c_int32], vp),
         "lbm_batch_destroy": ([vp], None),
     }
@@ -350,6 +352,17 @@ class Batch:
 
     def step(self, n: int, graph_steps: int = 0, stream=None):
         _check(LIB.lbm_batch_step(self.handle, int(n), int(graph_steps), _stream_handle(self.torch, stream)))
+
+    def set_launch(self, rows_per_wave: int, stream=None):
+        _check(LIB.lbm_batch_set_launch(self.handle, int(rows_per_wave), _stream_handle(self.torch, stream)))
+
+    def autotune(self, steps_per_trial: int = 3, stream=None) -> int:
+        """Pick the rows per wavefront on the batch itself; advances every run
+        by 8 * (steps_per_trial + 1) steps."""
+        rows = ctypes.c_int32()
+        _check(LIB.lbm_batch_autotune(self.handle, int(steps_per_trial), _stream_handle(self.torch, stream),
+                                      ctypes.byref(rows)))
+        return rows.value
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

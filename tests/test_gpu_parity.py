@@ -327,6 +327,27 @@ def test_batch_equals_single_runs(graph_steps):
         assert np.array_equal(m.get_f(), ref)
 
 
+def test_batch_set_launch_and_autotune():
+    """A batch re-chunked to another rows-per-wavefront still equals single
+    runs with that launch shape; the autotuner keeps one of its candidates and
+    its trial steps advance every member."""
+    specs = [make_params(70, 50, bc=1), make_params(33, 19)]
+    states = [random_state(p, 95 + i) for i, p in enumerate(specs)]
+    singles = [gpu_step_from(p, f, nsteps=3, launch=(5, 1)) for p, f in zip(specs, states)]
+    batch = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
+    for m, f in zip(batch.runs, states):
+        m.set_f(f)
+    batch.set_launch(5)
+    batch.step(3, graph_steps=2)
+    for m, ref in zip(batch.runs, singles):
+        assert np.array_equal(m.get_f(), ref)
+    rows = batch.autotune(1)
+    assert rows in (16, 32, 48, 64, 96, 128, 192, 256)
+    assert all(m.step_count == 3 + 8 * 2 for m in batch.runs)
+    st = batch.runs[0].reduce(1.0)
+    assert st["n_nonfinite"] == 0
+
+
 def test_rejects_bad_parameters():
     p = make_params(16, 16)
     p.dt = 0.5

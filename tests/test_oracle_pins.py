@@ -564,3 +564,30 @@ def test_shear_walls_drive_couette_profile():
     assert np.allclose(prof, -prof[::-1], atol=1e-12)
     assert 0 < slope[0] < 2 * 0.02 / (Ly - 1)
     assert np.max(np.abs(uy)) < 1e-12
+
+
+def test_flat_interface_coexistence_converges_to_maxwell():
+    """A relaxed flat liquid-vapour interface (a = 9/49, b = 2/21, T = 0.9 T_c,
+    tau = 0.8, dt = 1/4, CTU2) holds bulk densities near the Maxwell
+    construction (Sec. II E).  The departure is a spatial discretisation
+    error of the interface: resolving the interface by twice as many nodes
+    (kappa x 4) must shrink it by more than 2x on both branches."""
+    from oracle import thermo
+    a, b = 9.0 / 49.0, 2.0 / 21.0
+    T = 0.9 * 8 * a / (27 * b)
+    rv, rl = thermo.maxwell(T, a, b)
+    errs = []
+    for scale, Lx, nsteps in ((1, 64, 3000), (4, 128, 6000)):
+        x = np.arange(Lx)
+        w = 3.0 * math.sqrt(scale)
+        prof = rv + 0.5 * (rl - rv) * (np.tanh((x - (Lx / 4 - 0.5)) / w) - np.tanh((x - (3 * Lx / 4 - 0.5)) / w))
+        p = o.Params(Lx=Lx, Ly=1, T=T, a=a, b=b, kappa=scale / 6.125, tau=0.8, dt=0.25)
+        rho = prof[None, :]
+        f = o.run(p, o.init(p, rho, 0 * rho, 0 * rho), nsteps)
+        r = o.field_moments(p, f)[0][0]
+        liq = r[Lx // 2 - 4:Lx // 2 + 4].mean()
+        vap = np.concatenate([r[:4], r[-4:]]).mean()
+        errs.append((abs(liq / rl - 1), abs(vap / rv - 1)))
+    (l1, v1), (l4, v4) = errs
+    assert l1 < 0.012 and v1 < 0.10
+    assert l4 < l1 / 2 and v4 < v1 / 2
