@@ -77,3 +77,25 @@ def test_quiescent_bubble_growth_fp32_matches_fp64():
     print("R_eq every 2000 steps, FP64:", radii[lbm.FP64], "FP32-dev:", radii[lbm.FP32_DEV])
     assert np.all(np.diff(radii[lbm.FP64]) > 0) and radii[lbm.FP64][-1] > 150
     np.testing.assert_allclose(radii[lbm.FP32_DEV], radii[lbm.FP64], atol=0.01)
+
+
+def test_sheared_bubble_orientation_and_linear_deformation():
+    """Sheared cavitation (Sec. III C; 2048^2, walls at -+u_w with
+    u_w = shear_rate L / 2, T = 0.95 T_c, rho_ext = 0.95 rho_L, R = 30, FP32
+    deviation storage), 5000 steps: at small capillary number a drop in simple
+    shear tilts its major axis at 45 degrees to the flow and deforms linearly
+    in the shear rate (Taylor's small-deformation result)."""
+    from paper_1802_01272_amd import inputs as I
+    out = {}
+    for g in (5e-5, 1e-4):
+        w = I.sheared_bubble(g, 2048)
+        rho, ux, uy = w.fields()
+        run = lbm.Run(lbm.Params.from_workload(w, precision=lbm.FP32_DEV), rho, ux, uy)
+        run.step(5000)
+        out[g] = run.reduce(0.5 * (w.rho_vapour + w.rho_liquid))
+        run.close()
+    print({g: (s["R_eq"], s["D"], s["theta"]) for g, s in out.items()})
+    for s in out.values():
+        assert s["theta"] == pytest.approx(math.pi / 4, abs=0.06)
+        assert s["R_eq"] > 60  # the bubble grows in the superheated liquid
+    assert out[1e-4]["D"] / out[5e-5]["D"] == pytest.approx(2.0, rel=0.1)
