@@ -60,8 +60,8 @@ lbm_status validate(const lbm_params* p)
     if (!p) return fail(LBM_EINVAL, "null parameters");
     if (p->Lx < 1 || p->Ly < 1) return fail(LBM_EINVAL, "Lx and Ly must be >= 1");
     // eight FP64 distribution planes must fit in 4 GiB (32-bit buffer offsets)
-    if ((int64_t)p->Lx * (int64_t)p->Ly > (int64_t)1 << 26)
-        return fail(LBM_EINVAL, "Lx * Ly must not exceed 2^26 nodes (8192 x 8192)");
+    if ((int64_t)p->Lx * ((int64_t)p->Ly + (p->bc_y == LBM_SHEAR_WALLS ? 2 : 0)) > (int64_t)1 << 26)
+        return fail(LBM_EINVAL, "Lx * Ly (Lx * (Ly + 2) with walls) must not exceed 2^26 nodes");
     const double vals[] = {p->ds, p->dt, p->tau, p->T, p->a, p->b, p->kappa, p->rho_ref, p->u_wall, p->rho_wall,
                            p->clamp_radius, p->clamp_rho};
     for (double v : vals)
@@ -148,20 +148,47 @@ constexpr size_t COEF_BYTES = 8192;
 static_assert(sizeof(StepCoef<double>) + sizeof(StepCoef<float>) + 2 * ALIGN <= COEF_BYTES, "coef region");
 constexpr size_t RED_BYTES = (size_t)(REDUCE_MAX_BLOCKS + 1) * REDUCE_VALUES * sizeof(double);
 
-size_t field_bytes(const lbm_params* p) { return align_up((size_t)16 * p->Lx * p->Ly * storage_bytes(p)); }
+// stride of one distribution plane: the Lx * Ly lattice, then with shear walls
+// the two ghost rows (below, above)
+int64_t plane_of(const lbm_params* p)
+{
+    return (int64_t)p->Lx * ((int64_t)p->Ly + (p->bc_y == LBM_SHEAR_WALLS ? 2 : 0));
+}
+
+size_t field_bytes(const lbm_params* p) { return align_up((size_t)16 * (size_t)plane_of(p) * storage_bytes(p)); }
 
 size_t run_bytes(const lbm_params* p)
 {
     return COEF_BYTES + align_up(RED_BYTES) + 2 * field_bytes(p);
 }
 
-// default launch shape: enough wavefronts to fill 256 CUs x 4 SIMDs a few times over
+// default launch shape: one wavefront per SIMD, so a launch runs in rounds of
+// (SIMD count) wavefronts; each wavefront pays about 5 rows of warm-up for
+// its march (8 rows at roughly 60% of the cost of a full row).  Pick the rows
+// per wavefront that minimise rounds x (rows + 5).
 Launch default_launch(const lbm_params* p)
 {
-    const int nstrips = (p->Lx + STRIP - 1) / STRIP;
-    int rows = 128;
-    while (rows > 8 && (int64_t)nstrips * ((p->Ly + rows - 1) / rows) < 4096) rows /= 2;
-    return Launch{rows, 2};
+    static int slots = 0;
+    if (slots == 0) {
+        int dev = 0, ncu = 0;
+        slots = (hipGetDevice(&dev) == hipSuccess
+                 && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+                    ? 4 * ncu
+                    : 1024;
+    }
+    const int64_t nstrips = (p->Lx + STRIP - 1) / STRIP;
+    int best_rows = 64;
+    double best = 1e300;
+    for (int rows = 8; rows <= 512; rows += 8) {
+        const int64_t nwaves = nstrips * ((p->Ly + rows - 1) / rows);
+        const int64_t rounds = (nwaves + slots - 1) / slots;
+        const double cost = (double)rounds * (double)(std::min(rows, p->Ly) + 5);
+        if (cost < best - 1e-9) {
+            best = cost;
+            best_rows = rows;
+        }
+    }
+    return Launch{best_rows, 2};
 }
 
 // LDS of a step workgroup: the kernels keep the advected rows that wait for
@@ -174,7 +201,8 @@ size_t step_lds_bytes(const lbm_params* p, int wpg)
 bool launch_fits(const lbm_params* p, int wpg) { return step_lds_bytes(p, wpg) <= MAX_STEP_LDS; }
 
 std::mutex g_tune_mutex;
-std::map<std::tuple<int, int, int, int, int>, Launch> g_tuned;  // (Lx, Ly, precision, scheme, regularize)
+// (Lx, Ly, precision, scheme, regularize, bc_y)
+std::map<std::tuple<int, int, int, int, int, int>, Launch> g_tuned;
 
 }  // namespace
 
@@ -213,6 +241,19 @@ namespace {
 template <typename R>
 StepCoef<R>* coef_of(lbm_run* r) { return static_cast<StepCoef<R>*>(r->coef); }
 
+// (Re)write the two wall ghost rows of field `fld` (no-op without walls).
+// Every use of the non-current field as FP64 staging overwrites them.
+hipError_t fill_ghosts(lbm_run* r, int fld, hipStream_t s)
+{
+    if (r->p.bc_y != LBM_SHEAR_WALLS) return hipSuccess;
+    const int64_t plane = (int64_t)r->p.Lx * ((int64_t)r->p.Ly + 2);
+    return (r->p.precision == LBM_FP32_DEV)
+               ? launch_fill_ghost<float>(reinterpret_cast<float*>(r->field[fld]), static_cast<StepCoef<float>*>(r->coef),
+                                          r->p.Lx, r->p.Ly, plane, s)
+               : launch_fill_ghost<double>(reinterpret_cast<double*>(r->field[fld]), static_cast<StepCoef<double>*>(r->coef),
+                                           r->p.Lx, r->p.Ly, plane, s);
+}
+
 template <typename R>
 lbm_status upload_coef(lbm_run* r, hipStream_t s)
 {
@@ -239,7 +280,7 @@ lbm_status carve(const lbm_params* p, void* d_ws, size_t ws_bytes, lbm_run* r)
     r->step = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
-        auto it = g_tuned.find({p->Lx, p->Ly, p->precision, p->scheme, p->regularize});
+        auto it = g_tuned.find({p->Lx, p->Ly, p->precision, p->scheme, p->regularize, p->bc_y});
         r->launch = (it != g_tuned.end()) ? it->second : default_launch(p);
     }
     return LBM_OK;
@@ -263,7 +304,7 @@ RunView<R> view(lbm_run* r)
     v.Ly = r->p.Ly;
     v.rows = r->launch.rows_per_wave;
     v.nstrips = (r->p.Lx + STRIP - 1) / STRIP;
-    v.plane = nodes(r);
+    v.plane = plane_of(&r->p);
     return v;
 }
 
@@ -325,9 +366,12 @@ lbm_status init_common(const lbm_params* p, void* d_ws, size_t ws_bytes, void* s
         d_ux = stage + n;
         d_uy = stage + 2 * n;
     }
+    const int64_t plane = plane_of(p);
     hipError_t e = (p->precision == LBM_FP32_DEV)
-                       ? launch_init<float>(reinterpret_cast<float*>(r->field[0]), coef_of<float>(r), d_rho, d_ux, d_uy, n, s)
-                       : launch_init<double>(reinterpret_cast<double*>(r->field[0]), coef_of<double>(r), d_rho, d_ux, d_uy, n, s);
+                       ? launch_init<float>(reinterpret_cast<float*>(r->field[0]), coef_of<float>(r), d_rho, d_ux, d_uy, n, plane, s)
+                       : launch_init<double>(reinterpret_cast<double*>(r->field[0]), coef_of<double>(r), d_rho, d_ux, d_uy, n, plane, s);
+    // ghost rows of both fields (the second after its staging use above)
+    for (int fld = 0; fld < 2 && e == hipSuccess; ++fld) e = fill_ghosts(r, fld, s);
     if (e == hipSuccess && host) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         delete r;
@@ -342,8 +386,8 @@ lbm_status moments_to(lbm_run* r, double* rho, double* ux, double* uy, hipStream
 {
     const int64_t n = nodes(r);
     hipError_t e = (r->p.precision == LBM_FP32_DEV)
-                       ? launch_moments<float>(reinterpret_cast<const float*>(r->field[r->cur]), coef_of<float>(r), rho, ux, uy, n, s)
-                       : launch_moments<double>(reinterpret_cast<const double*>(r->field[r->cur]), coef_of<double>(r), rho, ux, uy, n, s);
+                       ? launch_moments<float>(reinterpret_cast<const float*>(r->field[r->cur]), coef_of<float>(r), rho, ux, uy, n, plane_of(&r->p), s)
+                       : launch_moments<double>(reinterpret_cast<const double*>(r->field[r->cur]), coef_of<double>(r), rho, ux, uy, n, plane_of(&r->p), s);
     if (e != hipSuccess) return hip_fail(e, "moments");
     return LBM_OK;
 }
@@ -352,8 +396,8 @@ lbm_status get_plane(lbm_run* r, int k, double* d_out, hipStream_t s)
 {
     const int64_t n = nodes(r);
     hipError_t e = (r->p.precision == LBM_FP32_DEV)
-                       ? launch_get_plane<float>(reinterpret_cast<const float*>(r->field[r->cur]), coef_of<float>(r), k, d_out, n, s)
-                       : launch_get_plane<double>(reinterpret_cast<const double*>(r->field[r->cur]), coef_of<double>(r), k, d_out, n, s);
+                       ? launch_get_plane<float>(reinterpret_cast<const float*>(r->field[r->cur]), coef_of<float>(r), k, d_out, n, plane_of(&r->p), s)
+                       : launch_get_plane<double>(reinterpret_cast<const double*>(r->field[r->cur]), coef_of<double>(r), k, d_out, n, plane_of(&r->p), s);
     if (e != hipSuccess) return hip_fail(e, "get_f");
     return LBM_OK;
 }
@@ -362,8 +406,8 @@ lbm_status set_plane(lbm_run* r, int k, const double* d_in, hipStream_t s)
 {
     const int64_t n = nodes(r);
     hipError_t e = (r->p.precision == LBM_FP32_DEV)
-                       ? launch_set_plane<float>(reinterpret_cast<float*>(r->field[r->cur]), coef_of<float>(r), k, d_in, n, s)
-                       : launch_set_plane<double>(reinterpret_cast<double*>(r->field[r->cur]), coef_of<double>(r), k, d_in, n, s);
+                       ? launch_set_plane<float>(reinterpret_cast<float*>(r->field[r->cur]), coef_of<float>(r), k, d_in, n, plane_of(&r->p), s)
+                       : launch_set_plane<double>(reinterpret_cast<double*>(r->field[r->cur]), coef_of<double>(r), k, d_in, n, plane_of(&r->p), s);
     if (e != hipSuccess) return hip_fail(e, "set_f");
     return LBM_OK;
 }
@@ -508,6 +552,7 @@ lbm_status lbm_moments(lbm_run* run, double* h_rho, double* h_ux, double* h_uy, 
     HIP_TRY(hipMemcpyAsync(h_rho, stage, n * sizeof(double), hipMemcpyDeviceToHost, s), "moments download");
     HIP_TRY(hipMemcpyAsync(h_ux, stage + n, n * sizeof(double), hipMemcpyDeviceToHost, s), "moments download");
     HIP_TRY(hipMemcpyAsync(h_uy, stage + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, s), "moments download");
+    HIP_TRY(fill_ghosts(run, run->cur ^ 1, s), "moments: ghost rows");
     HIP_TRY(hipStreamSynchronize(s), "moments download");
     return LBM_OK;
 }
@@ -546,6 +591,7 @@ lbm_status lbm_get_f(lbm_run* run, double* h_f, void* stream)
         HIP_TRY(hipMemcpyAsync(h_f + k * n, stage, n * sizeof(double), hipMemcpyDeviceToHost, s), "get_f download");
         HIP_TRY(hipStreamSynchronize(s), "get_f download");
     }
+    HIP_TRY(fill_ghosts(run, run->cur ^ 1, s), "get_f: ghost rows");
     return LBM_OK;
 }
 
@@ -561,6 +607,7 @@ lbm_status lbm_set_f(lbm_run* run, const double* h_f, void* stream)
         if (st != LBM_OK) return st;
         HIP_TRY(hipStreamSynchronize(s), "set_f upload");
     }
+    HIP_TRY(fill_ghosts(run, run->cur ^ 1, s), "set_f: ghost rows");
     return LBM_OK;
 }
 
@@ -572,9 +619,11 @@ lbm_status lbm_reduce(lbm_run* run, double rho_threshold, lbm_stats* out, void* 
     double* result = run->red + (size_t)REDUCE_MAX_BLOCKS * REDUCE_VALUES;
     hipError_t e = (run->p.precision == LBM_FP32_DEV)
                        ? launch_reduce<float>(reinterpret_cast<const float*>(run->field[run->cur]), coef_of<float>(run),
-                                              run->p.Lx, run->p.Ly, rho_threshold, run->red, REDUCE_MAX_BLOCKS, result, s)
+                                              run->p.Lx, run->p.Ly, plane_of(&run->p), rho_threshold, run->red,
+                                              REDUCE_MAX_BLOCKS, result, s)
                        : launch_reduce<double>(reinterpret_cast<const double*>(run->field[run->cur]), coef_of<double>(run),
-                                               run->p.Lx, run->p.Ly, rho_threshold, run->red, REDUCE_MAX_BLOCKS, result, s);
+                                               run->p.Lx, run->p.Ly, plane_of(&run->p), rho_threshold, run->red,
+                                               REDUCE_MAX_BLOCKS, result, s);
     if (e != hipSuccess) return hip_fail(e, "reduce");
     double v[REDUCE_VALUES];
     HIP_TRY(hipMemcpyAsync(v, result, sizeof(v), hipMemcpyDeviceToHost, s), "reduce download");
@@ -626,12 +675,19 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_ws, size_t ws_bytes, void* 
         HIP_TRY(hipMemcpyAsync(stage + n, z.data(), n * sizeof(double), hipMemcpyHostToDevice, s), "autotune");
         HIP_TRY(hipMemcpyAsync(stage + 2 * n, z.data(), n * sizeof(double), hipMemcpyHostToDevice, s), "autotune");
         hipError_t e = (p->precision == LBM_FP32_DEV)
-                           ? launch_init<float>(reinterpret_cast<float*>(r.field[0]), coef_of<float>(&r), stage, stage + n, stage + 2 * n, n, s)
-                           : launch_init<double>(reinterpret_cast<double*>(r.field[0]), coef_of<double>(&r), stage, stage + n, stage + 2 * n, n, s);
+                           ? launch_init<float>(reinterpret_cast<float*>(r.field[0]), coef_of<float>(&r), stage, stage + n, stage + 2 * n, n, plane_of(p), s)
+                           : launch_init<double>(reinterpret_cast<double*>(r.field[0]), coef_of<double>(&r), stage, stage + n, stage + 2 * n, n, plane_of(p), s);
+        for (int fld = 0; fld < 2 && e == hipSuccess; ++fld) e = fill_ghosts(&r, fld, s);
         if (e != hipSuccess) return hip_fail(e, "autotune init");
         HIP_TRY(hipStreamSynchronize(s), "autotune init");
     }
-    const int rows_c[] = {8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+    // fixed candidates plus the default shape's rows and its neighbours
+    std::vector<int> rows_c = {8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+    {
+        const int d = default_launch(p).rows_per_wave;
+        for (int r : {d - 16, d - 8, d, d + 8, d + 16})
+            if (r >= 8 && std::find(rows_c.begin(), rows_c.end(), r) == rows_c.end()) rows_c.push_back(r);
+    }
     const int wpg_c[] = {1, 2, 4};
     double best = 1e300;
     Launch bl = default_launch(p);
@@ -655,7 +711,7 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_ws, size_t ws_bytes, void* 
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
-        g_tuned[{p->Lx, p->Ly, p->precision, p->scheme, p->regularize}] = bl;
+        g_tuned[{p->Lx, p->Ly, p->precision, p->scheme, p->regularize, p->bc_y}] = bl;
     }
     *rows_per_wave = bl.rows_per_wave;
     *waves_per_group = bl.waves_per_group;
@@ -709,7 +765,7 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
         br.Ly = r.p.Ly;
         br.rows = r.launch.rows_per_wave;
         br.nstrips = (r.p.Lx + STRIP - 1) / STRIP;
-        br.plane = nodes(&r);
+        br.plane = plane_of(&r.p);
         fill_coef<R>(&r.p, coefs[i]);
         const int nchunks = (r.p.Ly + br.rows - 1) / br.rows;
         std::vector<BatchItem>& dst = (r.p.bc_y == LBM_SHEAR_WALLS) ? wall_items : items;

@@ -96,7 +96,8 @@ struct RunView {
     int32_t Lx, Ly;
     int32_t rows;       // rows per wavefront
     int32_t nstrips;    // wavefront strips along x
-    int64_t plane;      // Lx * Ly
+    int64_t plane;      // stride of one distribution plane: Lx * Ly, plus two
+                        // ghost rows (Lx * (Ly + 2)) with shear walls
 };
 
 // Work item of the batched launch.
@@ -129,18 +130,21 @@ hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coe
                              int regularize, int walls, int waves_per_group, hipStream_t s);
 template <typename R>
 hipError_t launch_init(R* f, const StepCoef<R>* coef, const double* rho, const double* ux,
-                       const double* uy, int64_t n, hipStream_t s);
+                       const double* uy, int64_t n, int64_t plane, hipStream_t s);
+template <typename R>
+hipError_t launch_fill_ghost(R* f, const StepCoef<R>* coef, int32_t Lx, int32_t Ly, int64_t plane,
+                             hipStream_t s);
 template <typename R>
 hipError_t launch_moments(const R* f, const StepCoef<R>* coef, double* rho, double* ux, double* uy,
-                          int64_t n, hipStream_t s);
+                          int64_t n, int64_t plane, hipStream_t s);
 template <typename R>
 hipError_t launch_get_plane(const R* f, const StepCoef<R>* coef, int k, double* out, int64_t n,
-                            hipStream_t s);
+                            int64_t plane, hipStream_t s);
 template <typename R>
 hipError_t launch_set_plane(R* f, const StepCoef<R>* coef, int k, const double* in, int64_t n,
-                            hipStream_t s);
+                            int64_t plane, hipStream_t s);
 template <typename R>
-hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_t Ly,
+hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_t Ly, int64_t plane,
                          double threshold, double* partials, int32_t max_blocks, double* result,
                          hipStream_t s);
 

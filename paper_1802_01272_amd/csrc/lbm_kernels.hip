@@ -194,38 +194,18 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     const uint32_t pbytes = (uint32_t)(plane * (int64_t)sizeof(R));
 
     // where row r comes from: a lattice row (wrapped periodically), or with
-    // walls one of the two ghost-row states (-1 below, +1 above)
-    auto row_src = [&](int r, uint32_t& voff, int& ghost) {
-        ghost = 0;
+    // walls one of the two ghost rows stored after the lattice rows of each
+    // plane (row Ly below the lattice, row Ly + 1 above).  No branch: the
+    // row index is selected on the scalar unit.
+    auto row_voff = [&](int r) -> uint32_t {
+        int rr;
         if constexpr (WALLS) {
-            if (r < 0) ghost = -1;
-            else if (r >= Ly) ghost = 1;
+            rr = (r < 0) ? Ly : ((r >= Ly) ? Ly + 1 : r);
+        } else {
+            rr = r % Ly;
+            if (rr < 0) rr += Ly;
         }
-        int rr = r % Ly;
-        if (rr < 0) rr += Ly;
-        voff = ((uint32_t)rr * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
-    };
-    // The two ghost-row states are read per use through a buffer descriptor
-    // over the coefficients (vector loads), so that their 32 values are not
-    // hoisted into registers for the whole march.
-    const __amdgpu_buffer_rsrc_t coef_rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void*)C, (short)0, (int)sizeof(StepCoef<R>), 0x00020000);
-    auto ghost_value = [&](int k, bool low) -> R {
-        const uint32_t off = (uint32_t)(low ? offsetof(StepCoef<R>, ghost_lo) : offsetof(StepCoef<R>, ghost_hi))
-                           + (uint32_t)k * (uint32_t)sizeof(R);
-        if constexpr (sizeof(R) == 4)
-            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(coef_rsrc, off, 0u, 0));
-        else
-            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(coef_rsrc, off, 0u, 0));
-    };
-    auto load_one = [&](int k, uint32_t voff, int ghost, R& v) {
-        if constexpr (WALLS) {
-            if (ghost) {
-                v = ghost_value(k, ghost < 0);
-                return;
-            }
-        }
-        buf_load(v, src, k, voff, pbytes);
+        return ((uint32_t)rr * (uint32_t)Lx + (uint32_t)col) * (uint32_t)sizeof(R);
     };
 
     // Rings of four rows per velocity, indexed by phase P (= t mod 4): B[P]
@@ -256,11 +236,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
 #pragma unroll
     for (int k = 0; k < 16; ++k) cD1[k] = cY[k] = cdX[k] = R(0);
     {
-        uint32_t voff;
-        int ghost;
-        row_src(y0 - 4, voff, ghost);
+        const uint32_t voff = row_voff(y0 - 4);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) load_one(k, voff, ghost, B[0][k]);
+        for (int k = 0; k < 16; ++k) buf_load(B[0][k], src, k, voff, pbytes);
     }
 
     // COLL = false: the first eight rows of the march only fill the rings
@@ -289,11 +267,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         for (int k = 0; k < 16; ++k)
             if (sign_y(k) > 0) D2m[k] = fm1[k] - f0[k];
         {
-            uint32_t nvoff;
-            int nghost;
-            row_src(r + 1, nvoff, nghost);
+            const uint32_t nvoff = row_voff(r + 1);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) load_one(k, nvoff, nghost, fm1[k]);
+            for (int k = 0; k < 16; ++k) buf_load(fm1[k], src, k, nvoff, pbytes);
         }
 
         // --- first step of the split: advection of row a -----------------------
@@ -348,19 +324,17 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     cY[K] = Y1;
                 }
             }
-            fs[K] = fj + inc;
+            // wall ghost rows are boundary values: they keep their state
+            // (row a as loaded; a select, not a branch)
+            fs[K] = ghost_a ? fj : fj + inc;
         });
-        // wall ghost rows are boundary values: they keep their state
-        if (ghost_a) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) fs[k] = ghost_value(k, a < 0);
-        }
 
         // --- regularization of the advected row (Eq. ereg): project onto the
         // Hermite space of order <= 3.  Linear in f and exact on w_k rho_ref,
-        // so it acts on the stored deviations as they are.
+        // so it acts on the stored deviations as they are; a wall ghost state
+        // (an equilibrium) is left as it is by the projection.
         if constexpr (REG) {
-            if (!ghost_a) {
+            {
                 N c[4][4];  // c[m][n] = sum_k d_k He_m(xi_x) He_n(xi_y), m + n <= 3
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
@@ -409,14 +383,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         }
 
         // --- advected density of row a and the force stencils (Eq. eder) -----
-        N ds_r;
-        if (ghost_a) {
-            ds_r = ((a < 0) ? C->ghost_rho_lo : C->ghost_rho_hi) - C->rho0;
-        } else {
-            ds_r = (N)fs[0];
+        N ds_r = (N)fs[0];
 #pragma unroll
-            for (int k = 1; k < 16; ++k) ds_r += (N)fs[k];
-        }
+        for (int k = 1; k < 16; ++k) ds_r += (N)fs[k];
         if constexpr (PEND_LDS) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) pend[(iN * 16 + k) * WAVE + lane] = fs[k];
@@ -671,27 +640,28 @@ __device__ __forceinline__ double feq_k(int k, double T, double rho, double ux, 
 
 template <typename R>
 __global__ void init_kernel(R* __restrict__ f, const StepCoef<R>* __restrict__ C, const double* __restrict__ rho,
-                            const double* __restrict__ ux, const double* __restrict__ uy, int64_t n)
+                            const double* __restrict__ ux, const double* __restrict__ uy, int64_t n,
+                            int64_t plane)
 {
     const double T = (double)C->T;
     const double rho0 = (double)C->rho0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double r = rho[i], vx = ux[i], vy = uy[i];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) f[k * n + i] = (R)(feq_k(k, T, r, vx, vy) - weight(k) * rho0);
+        for (int k = 0; k < 16; ++k) f[k * plane + i] = (R)(feq_k(k, T, r, vx, vy) - weight(k) * rho0);
     }
 }
 
 template <typename R>
 __global__ void moments_kernel(const R* __restrict__ f, const StepCoef<R>* __restrict__ C, double* __restrict__ rho,
-                               double* __restrict__ ux, double* __restrict__ uy, int64_t n)
+                               double* __restrict__ ux, double* __restrict__ uy, int64_t n, int64_t plane)
 {
     const double rho0 = (double)C->rho0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double r = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const double v = (double)f[k * n + i] + weight(k) * rho0;
+            const double v = (double)f[k * plane + i] + weight(k) * rho0;
             r += v;
             jx += v * xi_x(k);
             jy += v * xi_y(k);
@@ -704,27 +674,41 @@ __global__ void moments_kernel(const R* __restrict__ f, const StepCoef<R>* __res
 
 template <typename R>
 __global__ void get_plane_kernel(const R* __restrict__ f, const StepCoef<R>* __restrict__ C, int k,
-                                 double* __restrict__ out, int64_t n)
+                                 double* __restrict__ out, int64_t n, int64_t plane)
 {
     const double off = weight(k) * (double)C->rho0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (double)f[k * n + i] + off;
+        out[i] = (double)f[k * plane + i] + off;
 }
 
 template <typename R>
 __global__ void set_plane_kernel(R* __restrict__ f, const StepCoef<R>* __restrict__ C, int k,
-                                 const double* __restrict__ in, int64_t n)
+                                 const double* __restrict__ in, int64_t n, int64_t plane)
 {
     const double off = weight(k) * (double)C->rho0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        f[k * n + i] = (R)(in[i] - off);
+        f[k * plane + i] = (R)(in[i] - off);
+}
+
+// Wall ghost rows, stored after the Ly lattice rows of every plane: row Ly
+// holds the state below the lattice, row Ly + 1 the state above it.
+template <typename R>
+__global__ void fill_ghost_kernel(R* __restrict__ f, const StepCoef<R>* __restrict__ C, int Lx, int Ly,
+                                  int64_t plane)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * (int64_t)Lx;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const bool low = i < Lx;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) f[k * plane + (int64_t)Ly * Lx + i] = low ? C->ghost_lo[k] : C->ghost_hi[k];
+    }
 }
 
 // FP64 sums over the lattice: mass, momentum, bubble count, non-finite count
 // and the first and second position moments of the bubble (rho < threshold).
 template <typename R>
 __global__ __launch_bounds__(256) void reduce_kernel(const R* __restrict__ f, const StepCoef<R>* __restrict__ C,
-                                                     int Lx, int Ly, double threshold,
+                                                     int Lx, int Ly, int64_t plane, double threshold,
                                                      double* __restrict__ partials)
 {
     const int64_t n = (int64_t)Lx * Ly;
@@ -738,7 +722,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const R* __restrict__ f, co
         bool finite = true;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const double v = (double)f[k * n + i] + weight(k) * rho0;
+            const double v = (double)f[k * plane + i] + weight(k) * rho0;
             finite = finite && isfinite(v);
             r += v;
             jx += v * xi_x(k);
@@ -860,41 +844,51 @@ hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coe
 
 template <typename R>
 hipError_t launch_init(R* f, const StepCoef<R>* coef, const double* rho, const double* ux, const double* uy,
-                       int64_t n, hipStream_t s)
+                       int64_t n, int64_t plane, hipStream_t s)
 {
-    hipLaunchKernelGGL((init_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, rho, ux, uy, n);
+    hipLaunchKernelGGL((init_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, rho, ux, uy, n, plane);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fill_ghost(R* f, const StepCoef<R>* coef, int32_t Lx, int32_t Ly, int64_t plane, hipStream_t s)
+{
+    hipLaunchKernelGGL((fill_ghost_kernel<R>), dim3(grid_for(2 * (int64_t)Lx, 256)), dim3(256), 0, s, f, coef, Lx, Ly,
+                       plane);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_moments(const R* f, const StepCoef<R>* coef, double* rho, double* ux, double* uy, int64_t n,
-                          hipStream_t s)
+                          int64_t plane, hipStream_t s)
 {
-    hipLaunchKernelGGL((moments_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, rho, ux, uy, n);
+    hipLaunchKernelGGL((moments_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, rho, ux, uy, n, plane);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_get_plane(const R* f, const StepCoef<R>* coef, int k, double* out, int64_t n, hipStream_t s)
+hipError_t launch_get_plane(const R* f, const StepCoef<R>* coef, int k, double* out, int64_t n, int64_t plane,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL((get_plane_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, k, out, n);
+    hipLaunchKernelGGL((get_plane_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, k, out, n, plane);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_set_plane(R* f, const StepCoef<R>* coef, int k, const double* in, int64_t n, hipStream_t s)
+hipError_t launch_set_plane(R* f, const StepCoef<R>* coef, int k, const double* in, int64_t n, int64_t plane,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL((set_plane_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, k, in, n);
+    hipLaunchKernelGGL((set_plane_kernel<R>), dim3(grid_for(n, 256)), dim3(256), 0, s, f, coef, k, in, n, plane);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_t Ly, double threshold,
-                         double* partials, int32_t max_blocks, double* result, hipStream_t s)
+hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_t Ly, int64_t plane,
+                         double threshold, double* partials, int32_t max_blocks, double* result, hipStream_t s)
 {
     int nb = grid_for((int64_t)Lx * Ly, 256);
     if (nb > max_blocks) nb = max_blocks;
-    hipLaunchKernelGGL((reduce_kernel<R>), dim3(nb), dim3(256), 0, s, f, coef, Lx, Ly, threshold, partials);
+    hipLaunchKernelGGL((reduce_kernel<R>), dim3(nb), dim3(256), 0, s, f, coef, Lx, Ly, plane, threshold, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, s, partials, nb, result);
@@ -906,13 +900,16 @@ hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_
     template hipError_t launch_batch_step<R>(const BatchRun<R>*, const StepCoef<R>*, const BatchItem*,       \
                                              int32_t, int32_t, int, int, int, int, hipStream_t);             \
     template hipError_t launch_init<R>(R*, const StepCoef<R>*, const double*, const double*, const double*, \
-                                       int64_t, hipStream_t);                                                \
+                                       int64_t, int64_t, hipStream_t);                                       \
+    template hipError_t launch_fill_ghost<R>(R*, const StepCoef<R>*, int32_t, int32_t, int64_t, hipStream_t); \
     template hipError_t launch_moments<R>(const R*, const StepCoef<R>*, double*, double*, double*, int64_t, \
-                                          hipStream_t);                                                      \
-    template hipError_t launch_get_plane<R>(const R*, const StepCoef<R>*, int, double*, int64_t, hipStream_t); \
-    template hipError_t launch_set_plane<R>(R*, const StepCoef<R>*, int, const double*, int64_t, hipStream_t); \
-    template hipError_t launch_reduce<R>(const R*, const StepCoef<R>*, int32_t, int32_t, double, double*,    \
-                                         int32_t, double*, hipStream_t);
+                                          int64_t, hipStream_t);                                             \
+    template hipError_t launch_get_plane<R>(const R*, const StepCoef<R>*, int, double*, int64_t, int64_t,    \
+                                            hipStream_t);                                                    \
+    template hipError_t launch_set_plane<R>(R*, const StepCoef<R>*, int, const double*, int64_t, int64_t,    \
+                                            hipStream_t);                                                    \
+    template hipError_t launch_reduce<R>(const R*, const StepCoef<R>*, int32_t, int32_t, int64_t, double,    \
+                                         double*, int32_t, double*, hipStream_t);
 LBM_INSTANTIATE(float)
 LBM_INSTANTIATE(double)
 #undef LBM_INSTANTIATE
