@@ -58,6 +58,7 @@ typedef enum {
 
 enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };     /* storage precision               */
 enum { LBM_PERIODIC = 0, LBM_SHEAR_WALLS = 1 }; /* boundary in y                 */
+enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_NEAREST = 1 }; /* FP32 storage rounding */
 
 /* Parameters of one run.  Names follow the paper (Sec. II and III). */
 typedef struct {
@@ -87,6 +88,15 @@ typedef struct {
                              its f_k rescaled to density clamp_rho (the fixed
                              far-field density of Sec. III B); <= 0: off      */
     double clamp_rho;     /* density imposed outside the circle, in (0, 1/b) */
+    int32_t rounding;     /* LBM_FP32_DEV only: how each new f_k - w_k rho_ref,
+                             computed in FP64, is rounded to FP32.
+                             LBM_ROUND_STOCHASTIC (0, the default): up or down
+                             with probabilities that make the stored value
+                             unbiased, so storage errors do not accumulate
+                             coherently over many steps; deterministic, from
+                             a hash of the run's step count and the node's own
+                             values.  LBM_ROUND_NEAREST: to nearest, ties to
+                             even.  Ignored for LBM_FP64.                       */
 } lbm_params;
 
 /* FP64 diagnostics of one state (Sec. III C).  Bubble = nodes with
@@ -139,8 +149,11 @@ lbm_status lbm_init_device(const lbm_params* p, void* d_ws, size_t ws_bytes, voi
                            lbm_run** out);
 
 /* Re-open a workspace that holds the state of a run after `step` steps (a
- * checkpoint taken by copying the workspace), without touching the device
- * data.  The parameters must equal those the state was created with. */
+ * checkpoint taken by copying the workspace).  The distribution fields are
+ * not touched; the coefficient block and the step counter that seeds the
+ * stochastic rounding are rewritten from p and step, so a reopened run
+ * continues exactly as the original would.  The parameters must equal those
+ * the state was created with. */
 lbm_status lbm_attach(const lbm_params* p, void* d_ws, size_t ws_bytes, int64_t step,
                       lbm_run** out);
 
@@ -181,9 +194,9 @@ lbm_status lbm_set_f_device(lbm_run* run, const double* d_f, void* stream);
 lbm_status lbm_reduce(lbm_run* run, double rho_threshold, lbm_stats* out, void* stream);
 
 /* Launch shape: rows of the lattice each wavefront advances (>= 1) and
- * wavefronts per workgroup (1, 2 or 4; at most 2 with FP64 storage, whose
- * kernels use 32 KiB of LDS per wavefront).  LBM_EINVAL otherwise.  Defaults
- * come from lbm_autotune or a built-in table. */
+ * wavefronts per workgroup (1 or 2: the step kernels keep 32 KiB of LDS per
+ * wavefront; 4 is refused).  LBM_EINVAL otherwise, and the previous shape is
+ * kept.  Defaults come from lbm_autotune or a built-in table. */
 lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per_group);
 lbm_status lbm_get_launch(const lbm_run* run, int32_t* rows_per_wave, int32_t* waves_per_group);
 

@@ -85,6 +85,8 @@ lbm_status validate(const lbm_params* p)
         if (p->clamp_rho <= 0 || (p->b > 0 && p->b * p->clamp_rho >= 1.0))
             return fail(LBM_EINVAL, "clamp_rho must lie in (0, 1/b)");
     }
+    if (p->rounding != LBM_ROUND_STOCHASTIC && p->rounding != LBM_ROUND_NEAREST)
+        return fail(LBM_EINVAL, "rounding must be LBM_ROUND_STOCHASTIC or LBM_ROUND_NEAREST");
     // CFL condition of the CTU schemes: max_k |xi_k,alpha| dt <= ds
     if (QL * p->dt > p->ds * (1.0 + 1e-12))
         return fail(LBM_ECFL, "CFL violated: dt * sqrt(3 + sqrt 6) must not exceed ds");
@@ -100,11 +102,9 @@ void fill_coef(const lbm_params* p, StepCoef<R>& c)
     const double q[2] = {QS, QL};
     for (int mx = 0; mx < 2; ++mx) {
         const double ax = nu * q[mx], k2x = q[mx] * (1 - ax);
-        c.a[mx] = (R)ax;
+        c.nu_xi[mx] = ax;
         for (int my = 0; my < 2; ++my) {
             const double ay = nu * q[my], k2y = q[my] * (1 - ay);
-            c.ab[mx][my] = (R)(ax * ay);
-            c.amab[mx][my] = (R)(ax - ax * ay);
             c.xs1[mx][my] = (R)(-nu * (1 - ay) * k2x);
             c.xs2[mx][my] = (R)(-nu * ay * k2x);
             c.ys1[mx][my] = (R)(-nu * (1 - ax) * k2y);
@@ -138,6 +138,7 @@ void fill_coef(const lbm_params* p, StepCoef<R>& c)
     c.clamp_cx = 0.5 * (p->Lx - 1);
     c.clamp_cy = 0.5 * (p->Ly - 1);
     c.clamp_rho = p->clamp_rho;
+    c.sr_mask = (p->rounding == LBM_ROUND_NEAREST) ? 0u : 0x1FFFFFFFu;
 }
 
 size_t storage_bytes(const lbm_params* p) { return p->precision == LBM_FP32_DEV ? 4 : 8; }
@@ -146,6 +147,9 @@ size_t storage_bytes(const lbm_params* p) { return p->precision == LBM_FP32_DEV 
 //   [coef (fp32 + fp64 tables)] [reduction partials + result] [field 0] [field 1]
 constexpr size_t COEF_BYTES = 8192;
 static_assert(sizeof(StepCoef<double>) + sizeof(StepCoef<float>) + 2 * ALIGN <= COEF_BYTES, "coef region");
+// the step counter pair of the stochastic rounding sits at the end of the coef region
+constexpr size_t SEQ_OFF = COEF_BYTES - 64;
+static_assert(sizeof(StepCoef<double>) <= SEQ_OFF && sizeof(StepCoef<float>) <= SEQ_OFF, "seq slot");
 constexpr size_t RED_BYTES = (size_t)(REDUCE_MAX_BLOCKS + 1) * REDUCE_VALUES * sizeof(double);
 
 // stride of one distribution plane: the Lx * Ly lattice, then with shear walls
@@ -192,11 +196,12 @@ Launch default_launch(const lbm_params* p)
 }
 
 // LDS of a step workgroup: the kernels keep the advected rows that wait for
-// their collision there (FP64 storage); capped at 64 KiB per workgroup
+// their collision there (32 KiB per wavefront); capped at 64 KiB per workgroup
 constexpr size_t MAX_STEP_LDS = 65536;
 size_t step_lds_bytes(const lbm_params* p, int wpg)
 {
-    return (size_t)wpg * (p->precision == LBM_FP32_DEV ? step_lds_per_wave<float>() : step_lds_per_wave<double>());
+    (void)p;
+    return (size_t)wpg * STEP_LDS_PER_WAVE;
 }
 bool launch_fits(const lbm_params* p, int wpg) { return step_lds_bytes(p, wpg) <= MAX_STEP_LDS; }
 
@@ -254,12 +259,17 @@ hipError_t fill_ghosts(lbm_run* r, int fld, hipStream_t s)
                                            r->p.Lx, r->p.Ly, plane, s);
 }
 
+uint32_t* seq_of(lbm_run* r) { return reinterpret_cast<uint32_t*>(r->ws + SEQ_OFF); }
+
+// coefficients, and the step counter pair set to the run's step (both slots)
 template <typename R>
 lbm_status upload_coef(lbm_run* r, hipStream_t s)
 {
     StepCoef<R> c;
     fill_coef<R>(&r->p, c);
+    const uint32_t seq[2] = {(uint32_t)r->step, (uint32_t)r->step};
     HIP_TRY(hipMemcpyAsync(r->coef, &c, sizeof(c), hipMemcpyHostToDevice, s), "upload coefficients");
+    HIP_TRY(hipMemcpyAsync(seq_of(r), seq, sizeof(seq), hipMemcpyHostToDevice, s), "upload step counter");
     HIP_TRY(hipStreamSynchronize(s), "upload coefficients");
     return LBM_OK;
 }
@@ -300,6 +310,8 @@ RunView<R> view(lbm_run* r)
     v.f_in = reinterpret_cast<const R*>(r->field[r->cur]);
     v.f_out = reinterpret_cast<R*>(r->field[r->cur ^ 1]);
     v.coef = coef_of<R>(r);
+    v.seq = seq_of(r);
+    v.cur = r->cur;
     v.Lx = r->p.Lx;
     v.Ly = r->p.Ly;
     v.rows = r->launch.rows_per_wave;
@@ -486,13 +498,15 @@ lbm_status lbm_attach(const lbm_params* p, void* d_ws, size_t ws_bytes, int64_t 
     lbm_run* r = new (std::nothrow) lbm_run();
     if (!r) return fail(LBM_EINVAL, "out of host memory");
     st = carve(p, d_ws, ws_bytes, r);
-    if (st == LBM_OK) st = upload_coef_any(r, nullptr);
+    if (st == LBM_OK) {
+        r->cur = (int)(step & 1);
+        r->step = step;
+        st = upload_coef_any(r, nullptr);
+    }
     if (st != LBM_OK) {
         delete r;
         return st;
     }
-    r->cur = (int)(step & 1);
-    r->step = step;
     *out = r;
     return LBM_OK;
 }
@@ -640,7 +654,7 @@ lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per
     if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
         return fail(LBM_EINVAL, "waves_per_group must be 1, 2 or 4");
     if (!launch_fits(&run->p, waves_per_group))
-        return fail(LBM_EINVAL, "waves_per_group too large for the LDS of this storage precision (FP64: at most 2)");
+        return fail(LBM_EINVAL, "waves_per_group too large for the LDS of the step kernel (at most 2)");
     run->launch = Launch{rows_per_wave, waves_per_group};
     return LBM_OK;
 }
@@ -761,6 +775,7 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
         br.f[0] = reinterpret_cast<R*>(r.field[0]);
         br.f[1] = reinterpret_cast<R*>(r.field[1]);
         br.coef = nullptr;
+        br.seq = seq_of(&r);
         br.Lx = r.p.Lx;
         br.Ly = r.p.Ly;
         br.rows = r.launch.rows_per_wave;

@@ -38,26 +38,20 @@ constexpr int HALO = 4;
 constexpr int STRIP = WAVE - 2 * HALO;
 
 // The step kernels hold the advected rows that wait for their collision (a
-// ring of four rows of 16 values per lane, indexed by the row phase) in LDS
-// for FP64 storage, in registers for FP32.
-template <typename R> struct PendingInLds { static constexpr bool value = sizeof(R) == 8; };
+// ring of four rows of 16 FP64 values per lane, indexed by the row phase) in
+// LDS: 32 KiB per wavefront.
 constexpr int PENDING_ROWS = 4;
-template <typename R>
-constexpr size_t step_lds_per_wave()
-{
-    return PendingInLds<R>::value ? (size_t)PENDING_ROWS * 16 * WAVE * sizeof(R) : 0;
-}
+constexpr size_t STEP_LDS_PER_WAVE = (size_t)PENDING_ROWS * 16 * WAVE * sizeof(double);
 
 // ---------------------------------------------------------------------------
 // Per-run coefficients, prepared on the host in the storage precision R and
 // read by the kernels through uniform (scalar) loads.
 template <typename R>
 struct StepCoef {
-    // advection, in the storage precision R, indexed by the magnitude class m
-    // of a velocity component (0: |xi| = QS, 1: |xi| = QL); nu = dt/ds
-    R a[2];        // nu |xi|                            (CTU1 increment weights)
-    R ab[2][2];    // a[mx] * a[my]
-    R amab[2][2];  // a[mx] - a[mx] * a[my]
+    // advection, indexed by the magnitude class m of a velocity component
+    // (0: |xi| = QS, 1: |xi| = QL); nu = dt/ds.  CTU1 weights in FP64, the
+    // CTU2 blend weights in the storage precision R.
+    double nu_xi[2];  // nu |xi|
     // CTU2: the limited corrections are kept unscaled, X' = S^x / k2[mx] and
     // Y' = S^y / k2[my] with k2 = |xi| (1 - nu |xi|); the scales are folded
     // into the blend weights of their differences, indexed [mx][my]:
@@ -81,6 +75,8 @@ struct StepCoef {
     double clamp_r2, clamp_cx, clamp_cy, clamp_rho;
     int32_t walls;
     int32_t clamp;
+    // FP32 storage rounding: 2^29 - 1 stochastic, 0 to nearest
+    uint32_t sr_mask;
 };
 
 // magnitude class of the x / y component of velocity k
@@ -93,6 +89,8 @@ struct RunView {
     const R* f_in;
     R* f_out;
     const StepCoef<R>* coef;
+    uint32_t* seq;      // step counter pair of the stochastic rounding
+    int32_t cur;        // f_in is field cur: the step reads seq[cur]
     int32_t Lx, Ly;
     int32_t rows;       // rows per wavefront
     int32_t nstrips;    // wavefront strips along x
@@ -109,6 +107,7 @@ template <typename R>
 struct BatchRun {
     R* f[2];
     const StepCoef<R>* coef;
+    uint32_t* seq;      // the run's step counter pair
     int32_t Lx, Ly;
     int32_t rows, nstrips;
     int64_t plane;

@@ -22,7 +22,7 @@
 //    the row two behind that is collided and stored.  Each value of f is read
 //    from HBM once per step (plus the 8-column and 8-row halo) and written
 //    once.  The advected rows that wait for their collision stay on chip, in
-//    registers (FP32) or in LDS (FP64).
+//    LDS, in FP64.
 //  * CTU2 is evaluated in an equivalent rearranged form: the CTU1 bilinear
 //    update (Eq. ctueq) plus, per node, the limited corrections X = S^x and
 //    Y = S^y (division-free MC limiter) computed once per node and blended
@@ -38,8 +38,12 @@
 //    advective increment A_k(f) - f is formed from upwind differences, so it
 //    is exactly zero on a constant field in any precision.  Node-local
 //    arithmetic (moments, stencils, collision and force) is FP64 in both
-//    storage modes: in FP32 its rounding acts as a small systematic forcing
-//    that accumulates step after step.
+//    storage modes.  With FP32 storage, every rounding that repeats identically
+//    from step to step where the flow is nearly steady adds up coherently, so
+//    the FP32 path keeps only roundings that do not: the upwind differences
+//    and the CTU2 corrections are FP32, the CTU1 sum and the advected value
+//    f + (A f - f) are FP64 (exact from the FP32 operands), and the new
+//    deviation is rounded to FP32 stochastically (unbiased, seeded per step).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -135,12 +139,46 @@ __device__ __forceinline__ double recip(double x)
     return __builtin_fma(y, e, y);
 }
 
-// compile-time choice between two arrays of one type
-template <bool FIRST, typename T>
-__device__ __forceinline__ T& pick(T& a, T& b)
+// Storage rounding of an FP64 result to FP32.  With mask = 2^29 - 1 it rounds
+// stochastically: a 29-bit offset u is added to the 29 low bits of the FP64
+// significand that FP32 drops, and those bits are then cleared, so the
+// magnitude rounds up with probability (dropped bits) / 2^29 and the stored
+// value is unbiased.  u is the low word of a partner value of the same node
+// XOR a per-step seed: for any fixed value, u is uniform over the seeds.  With
+// mask = 0 it is the conversion's round-to-nearest-even.
+__device__ __forceinline__ float store_round(double x, double partner, uint32_t seed, uint32_t mask)
 {
-    if constexpr (FIRST) return a;
-    else return b;
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t u = ((uint32_t)__builtin_bit_cast(uint64_t, partner) ^ seed) & mask;
+    const uint64_t t = b + u;
+    const uint64_t c = (t & 0xFFFFFFFF00000000ull) | (uint64_t)((uint32_t)t & ~mask);  // mask < 2^32
+    return (float)__builtin_bit_cast(double, c);
+}
+
+// 32-bit integer hash (the "lowbias32" finaliser of C. Wellons' hash-prospector)
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Seed of this step's stochastic rounding (FP32 storage): the run's step
+// counter seq[cur] hashed; the wavefront that owns strip 0 of chunk 0 writes
+// seq[cur] + 1 to the other slot, which the next step reads (steps alternate
+// cur like the two fields, so captured graphs keep advancing the seed).
+template <typename R>
+__device__ __forceinline__ uint32_t step_seed(uint32_t* seq, int cur, bool owner)
+{
+    if constexpr (sizeof(R) != 4) return 0u;
+    const uint32_t n = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(seq + cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (owner && (threadIdx.x & (WAVE - 1)) == 0)
+        __hip_atomic_store(seq + (cur ^ 1), n + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return mix32(n);
 }
 
 // minmod(a, b) = median(a, b, 0): 0 when the signs differ, else the smaller one
@@ -177,9 +215,8 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                                            const StepCoef<R>* __restrict__ C,
                                            const int Lx, const int Ly, const int64_t plane,
                                            const int strip, const int y0, const int y1,
-                                           R* __restrict__ pend)
+                                           double* __restrict__ pend, const uint32_t seed)
 {
-    constexpr bool PEND_LDS = PendingInLds<R>::value;
     using N = double;  // node-local arithmetic (moments, stencils, collision)
     const int lane = threadIdx.x & (WAVE - 1);
     int col = (strip * STRIP - HALO + lane) % Lx;
@@ -210,18 +247,20 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
 
     // Rings of four rows per velocity, indexed by phase P (= t mod 4): B[P]
     // holds the new row r, and B[P+1], B[P+2], B[P+3] (mod 4) hold rows a-1,
-    // a, a+1; S[P] receives the advected row a, and S[P+2], S[P+3] hold the
-    // advected rows a-2, a-1.  Roles move by index, never by copying.  Row
-    // r+1 is loaded during phase P into B[P+1] once row a-1 has been used.
-    // With PEND_LDS the advected rows wait instead in four LDS slots of this
-    // wavefront, indexed like S (each lane reads back only what it wrote, so
-    // no barrier is needed).
+    // a, a+1.  Roles move by index, never by copying.  Row r+1 is loaded
+    // during phase P into B[P+1] once row a-1 has been used.  The advected
+    // rows wait for their collision in four LDS slots of this wavefront,
+    // indexed the same way (slot P receives row a; slots P+2, P+3 hold rows
+    // a-2, a-1; each lane reads back only what it wrote, so no barrier is
+    // needed).  They are kept in FP64: with FP32 storage the advected value
+    // f + (A f - f) is the exact FP64 sum of two FP32 values, so the
+    // collision starts from it unrounded.
     R B[4][16];
-    R S[4][16];
     // carries per velocity: the upwind x-difference D1 of the row the CTU1
-    // part reuses, and for CTU2 Y' at row a and dX = X'_{i+1} - X'_i at row
-    // a-1 (s_y > 0) or a (s_y < 0)
-    R cD1[16], cY[16], cdX[16];
+    // part reuses (FP64, exact from the storage precision), and for CTU2 Y'
+    // at row a and dX = X'_{i+1} - X'_i at row a-1 (s_y > 0) or a (s_y < 0)
+    N cD1[16];
+    R cY[16], cdX[16];
     // per-row stencil rings (same indexing by phase): advected density
     // deviation sums and their x-sums (row a), Laplacian rows and their
     // x-differences and x-sums (row a-1), pending 24-neighbour gradient sums
@@ -230,11 +269,14 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) B[i][k] = S[i][k] = R(0);
+        for (int k = 0; k < 16; ++k) B[i][k] = R(0);
         dsr[i] = hsr[i] = Lr[i] = dLr[i] = sLr[i] = ax[i] = ay[i] = N(0);
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) cD1[k] = cY[k] = cdX[k] = R(0);
+    for (int k = 0; k < 16; ++k) {
+        cD1[k] = N(0);
+        cY[k] = cdX[k] = R(0);
+    }
     {
         const uint32_t voff = row_voff(y0 - 4);
 #pragma unroll
@@ -251,8 +293,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         R(&fm1)[16] = B[iM1];
         R(&f0)[16] = B[i0];
         R(&fp1)[16] = B[iP1];
-        R fsl[16];
-        R(&fs)[16] = pick<PEND_LDS>(fsl, S[iN]);   // advected row a (written here)
+        N fs[16];                                  // advected row a (written here)
         const int r = y0 - 4 + t;
         const int a = r - 2;
         const int o = a - 2;
@@ -278,19 +319,26 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             constexpr int SX = sign_x(K), SY = sign_y(K), MX = mag_x(K), MY = mag_y(K);
             const R fj = f0[K];
             // advective increment A_k(f) - f from upwind differences (exact on
-            // constants): with D1 = f(i - s_x) - f(i) on row a and on the row
-            // upwind in y, D2 = f(a - s_y) - f(a), the CTU1 part is
-            // a D1 + b D2 + a b (D1(a - s_y) - D1(a)), evaluated as
-            // (a - a b) D1(a) + b D2 + a b D1(a - s_y).  D1 of the row that is
-            // reused one row later is carried in cD1.
-            R inc;
+            // constants): with D1 = f(i - s_x) - f(i) on row a (Dc) and on the
+            // row upwind in y (Du), and D2 = f(a - s_y) - f(a), the CTU1 part
+            // is b D2 + a (Dc + b (Du - Dc)), a = nu |xi_x|, b = nu |xi_y|.  It
+            // is summed in FP64 from the FP32 differences (in FP32 storage
+            // mode the roundings of an FP32 sum repeat step after step where
+            // the flow is nearly steady and add up); D1 of the row that is
+            // reused one row later is carried in cD1.  The CTU2 corrections,
+            // second differences of limited slopes, stay in the storage
+            // precision.
+            const N ax = C->nu_xi[MX], ay = C->nu_xi[MY];
+            N adv;        // f + CTU1 part
+            R corr = 0;   // CTU2 corrections
             if constexpr (SY > 0) {
                 const R rx = fj - from_left(fj);          // R^x at row a
                 const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
                 const R D1 = (SX > 0) ? -rx : rxu;
                 const R D2 = D2m[K];
-                inc = C->amab[MX][MY] * D1 + C->a[MY] * D2 + C->ab[MX][MY] * cD1[K];
-                cD1[K] = D1;
+                const N Dc = (N)D1, Du = cD1[K];
+                adv = __builtin_fma(ay, (N)D2, (N)fj) + ax * __builtin_fma(ay, Du - Dc, Dc);
+                cD1[K] = Dc;
                 if constexpr (SCHEME == 2) {
                     // X' at row a and its x-difference; dX of row a-1 is carried
                     const R X = mc_half(rx, rxu);
@@ -298,7 +346,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     // Y' at row a+1 (ratio with R^y of row a = -D2); Y' of row a is carried
                     const R Y1 = mc_half(fp1[K] - fj, -D2);
                     const R dY = Y1 - cY[K];
-                    inc += C->xs1[MX][MY] * dXj + C->xs2[MX][MY] * cdX[K] + C->ys1[MX][MY] * dY
+                    corr = C->xs1[MX][MY] * dXj + C->xs2[MX][MY] * cdX[K] + C->ys1[MX][MY] * dY
                          + C->ys2[MX][MY] * upwind_x<SX>(dY);
                     cdX[K] = dXj;
                     cY[K] = Y1;
@@ -309,8 +357,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R rxu = upwind_x<SX>(rx);
                 const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row a+1
                 const R D2 = fjp - fj;
-                inc = C->amab[MX][MY] * cD1[K] + C->a[MY] * D2 + C->ab[MX][MY] * D1p;
-                cD1[K] = D1p;
+                const N Dc = cD1[K], Du = (N)D1p;
+                adv = __builtin_fma(ay, (N)D2, (N)fj) + ax * __builtin_fma(ay, Du - Dc, Dc);
+                cD1[K] = Du;
                 if constexpr (SCHEME == 2) {
                     // X' at row a+1 and its x-difference; dX of row a is carried
                     const R X = mc_half(rx, rxu);
@@ -318,7 +367,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     // Y' at row a+1 (ratio with R^y of row a+2); Y' of row a is carried
                     const R Y1 = mc_half(D2, cur[K] - fjp);
                     const R dY = Y1 - cY[K];
-                    inc += C->xs1[MX][MY] * cdX[K] + C->xs2[MX][MY] * dXjp + C->ys1[MX][MY] * dY
+                    corr = C->xs1[MX][MY] * cdX[K] + C->xs2[MX][MY] * dXjp + C->ys1[MX][MY] * dY
                          + C->ys2[MX][MY] * upwind_x<SX>(dY);
                     cdX[K] = dXjp;
                     cY[K] = Y1;
@@ -326,7 +375,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             }
             // wall ghost rows are boundary values: they keep their state
             // (row a as loaded; a select, not a branch)
-            fs[K] = ghost_a ? fj : fj + inc;
+            fs[K] = ghost_a ? (N)fj : adv + (N)corr;
         });
 
         // --- regularization of the advected row (Eq. ereg): project onto the
@@ -374,22 +423,20 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     const N EO = c[0][1] * hy[1] + c[0][3] * hy[3] + c[2][1] * (hx[2] * hy[1]);
                     const N OO = c[1][1] * (hx[1] * hy[1]);
                     const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
-                    fs[4 * G + 0] = (R)(w * (Pp + Sp));   // (+,+)
-                    fs[4 * G + 1] = (R)(w * (Pm - Sm));   // (-,+)
-                    fs[4 * G + 2] = (R)(w * (Pp - Sp));   // (-,-)
-                    fs[4 * G + 3] = (R)(w * (Pm + Sm));   // (+,-)
+                    fs[4 * G + 0] = w * (Pp + Sp);   // (+,+)
+                    fs[4 * G + 1] = w * (Pm - Sm);   // (-,+)
+                    fs[4 * G + 2] = w * (Pp - Sp);   // (-,-)
+                    fs[4 * G + 3] = w * (Pm + Sm);   // (+,-)
                 });
             }
         }
 
         // --- advected density of row a and the force stencils (Eq. eder) -----
-        N ds_r = (N)fs[0];
+        N ds_r = fs[0];
 #pragma unroll
-        for (int k = 1; k < 16; ++k) ds_r += (N)fs[k];
-        if constexpr (PEND_LDS) {
+        for (int k = 1; k < 16; ++k) ds_r += fs[k];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) pend[(iN * 16 + k) * WAVE + lane] = fs[k];
-        }
+        for (int k = 0; k < 16; ++k) pend[(iN * 16 + k) * WAVE + lane] = fs[k];
         const N rho_r = C->rho0 + ds_r;
         // p^i - p^w = rho T - rho T/(1 - b rho) + a rho^2 = rho^2 (a - b T/(1 - b rho))
         const N phi_r = rho_r * rho_r * (C->a_vdw - C->b_vdw * C->T * recip(1.0 - C->b_vdw * rho_r));
@@ -435,11 +482,8 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
 
         if constexpr (COLL) {
             // --- second step of the split: collision and force on row o ------------
-            // advected row o = a - 2: ring slot i0, in registers or in LDS
-            auto fo = [&](int k) -> R {
-                if constexpr (PEND_LDS) return pend[(i0 * 16 + k) * WAVE + lane];
-                else return S[i0][k];
-            };
+            // advected row o = a - 2: LDS ring slot i0
+            auto fo = [&](int k) -> N { return pend[(i0 * 16 + k) * WAVE + lane]; };
             // moments of the advected row o: u = sum f xi / rho, a2 = sum f (xi xi - I)
             // (w_k rho_ref drops out of both)
             N jx = 0, jy = 0, axx = 0, axy = 0, ayy = 0;
@@ -508,7 +552,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
 
             // f^{n+1}_k = A f*_k + w_k P_k for velocity 4G+s, from the even/odd
             // parts of the polynomial of group G, in FP64 with one rounding to
-            // the storage precision
+            // the storage precision (FP32: stochastic, the partner of velocity
+            // 4G+s is 4G+(s^1))
+            const uint32_t srm = C->sr_mask;
             static_for<0, 4>([&](auto gc) {
                 constexpr int G = decltype(gc)::value;
                 constexpr N qx = group_qx(G), qy = group_qy(G), wg = group_w(G);
@@ -518,10 +564,15 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const N OO = (qx * qy) * c11;
                 const N Pp = EE + OO, Pm = EE - OO, Sp = OE + EO, Sm = OE - EO;
                 const N poly[4] = {wg * (Pp + Sp), wg * (Pm - Sm), wg * (Pp - Sp), wg * (Pm + Sm)};
+                N xn[4];
+    #pragma unroll
+                for (int sv = 0; sv < 4; ++sv) xn[sv] = A * fo(4 * G + sv) + poly[sv];
     #pragma unroll
                 for (int sv = 0; sv < 4; ++sv) {
                     const int K = 4 * G + sv;
-                    const R fnew = (R)(A * (N)fo(K) + poly[sv]);
+                    R fnew;
+                    if constexpr (sizeof(R) == 4) fnew = store_round(xn[sv], xn[sv ^ 1], seed, srm);
+                    else fnew = (R)xn[sv];
                     if (store_row && out_lane) buf_store(fnew, dst, K, soff, pbytes);
                 }
             });
@@ -573,15 +624,11 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nblocks)
     return x * q + (x < rem ? x : rem) + i;
 }
 
-// dynamic LDS of a step workgroup: step_lds_per_wave<R>() bytes per wavefront
+// dynamic LDS of a step workgroup: STEP_LDS_PER_WAVE bytes per wavefront
 extern __shared__ __attribute__((aligned(16))) char step_lds[];
-template <typename R>
-__device__ __forceinline__ R* wave_lds()
+__device__ __forceinline__ double* wave_lds()
 {
-    if constexpr (PendingInLds<R>::value)
-        return reinterpret_cast<R*>(step_lds) + (threadIdx.x / WAVE) * (PENDING_ROWS * 16 * WAVE);
-    else
-        return nullptr;
+    return reinterpret_cast<double*>(step_lds) + (threadIdx.x / WAVE) * (PENDING_ROWS * 16 * WAVE);
 }
 
 // One wavefront per SIMD with the full register file (up to 512 registers,
@@ -591,6 +638,7 @@ template <typename R> struct WavesPerEU { static constexpr int value = 1; };
 template <typename R, int SCHEME, bool REG, bool WALLS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::value))) void step_kernel(const R* __restrict__ fin, R* __restrict__ fout,
                                                    const StepCoef<R>* __restrict__ coef,
+                                                   uint32_t* __restrict__ seq, int cur,
                                                    int Lx, int Ly, int64_t plane, int rows,
                                                    int nstrips, int nwaves)
 {
@@ -602,7 +650,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
     const int chunk = wave / nstrips, strip = wave - chunk * nstrips;
     const int y0 = chunk * rows;
     const int y1 = min(y0 + rows, Ly);
-    strip_step<R, SCHEME, REG, WALLS>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1, wave_lds<R>());
+    const uint32_t seed = step_seed<R>(seq, cur, wave == 0);
+    strip_step<R, SCHEME, REG, WALLS>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1, wave_lds(), seed);
 }
 
 template <typename R, int SCHEME, bool REG, bool WALLS>
@@ -621,8 +670,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
     const int y1 = min(y0 + run.rows, run.Ly);
     R* const fa = run.f[0];
     R* const fb = run.f[1];
+    const uint32_t seed = step_seed<R>(run.seq, cur, it.strip == 0 && it.chunk == 0);
     strip_step<R, SCHEME, REG, WALLS>(cur ? fb : fa, cur ? fa : fb, coefs + it.run,
-                                      run.Lx, run.Ly, run.plane, it.strip, y0, y1, wave_lds<R>());
+                                      run.Lx, run.Ly, run.plane, it.strip, y0, y1, wave_lds(), seed);
 }
 
 // ----------------------------------------------------------------------------
@@ -797,10 +847,10 @@ hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int wal
     const int nwaves = rv.nstrips * nchunks;
     const int nblocks = (nwaves + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
-    const size_t lds = wpg * step_lds_per_wave<R>();
+    const size_t lds = wpg * STEP_LDS_PER_WAVE;
 #define LBM_LAUNCH(SC, RG, WL)                                                                                \
-    hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, lds, s, rv.f_in, rv.f_out, rv.coef, rv.Lx, \
-                       rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
+    hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, lds, s, rv.f_in, rv.f_out, rv.coef, rv.seq, \
+                       rv.cur, rv.Lx, rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
 #define LBM_LAUNCH_W(SC, RG)          \
     if (walls) LBM_LAUNCH(SC, RG, true); \
     else LBM_LAUNCH(SC, RG, false)
@@ -824,7 +874,7 @@ hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coe
     if (nitems <= 0) return hipSuccess;
     const int nblocks = (nitems + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
-    const size_t lds = wpg * step_lds_per_wave<R>();
+    const size_t lds = wpg * STEP_LDS_PER_WAVE;
 #define LBM_LAUNCH(SC, RG, WL) \
     hipLaunchKernelGGL((batch_step_kernel<R, SC, RG, WL>), grid, block, lds, s, d_runs, d_coefs, d_items, nitems, cur)
 #define LBM_LAUNCH_W(SC, RG)          \

@@ -185,6 +185,13 @@ def _paper_fluid(T_over_Tc: float):
     return a, b, rv, rl
 
 
+def storage_reference(rho_vapour: float, rho_ext: float) -> float:
+    """rho_ref of the FP32 deviation storage for a bubble in liquid: midway
+    between the two phases, which halves the largest stored |f_k - w_k rho_ref|
+    (and its rounding) against a reference at either phase."""
+    return 0.5 * (rho_vapour + rho_ext)
+
+
 def quiescent_bubble(L: int = 1024, radius: float = 20.0) -> Workload:
     """Superheated liquid at T = 0.95 T_c, density 0.95 rho_L (coexistence),
     one vapour bubble (rho_V) of radius `radius` nodes at the centre, tau = 0.7,
@@ -193,7 +200,7 @@ def quiescent_bubble(L: int = 1024, radius: float = 20.0) -> Workload:
     rho_ext = 0.95 * rl
     return Workload("quiescent_bubble_%d" % L, L, L, T=0.95, a=a, b=b, kappa=1.0, tau=0.7,
                     steps=20000, rho_liquid=rl, rho_vapour=rv, rho_ext=rho_ext,
-                    rho_ref=rho_ext, shape="bubble", radius=radius)
+                    rho_ref=storage_reference(rv, rho_ext), shape="bubble", radius=radius)
 
 
 def large_lattice(L: int = 6144) -> Workload:
@@ -213,8 +220,8 @@ def sheared_bubble(shear_rate: float, L: int = 2048) -> Workload:
     rho_ext = 0.95 * rl
     return Workload("sheared_bubble_%d_%g" % (L, shear_rate), L, L, T=0.95, a=a, b=b,
                     kappa=1.0, tau=0.7, bc_y=1, u_wall=shear_rate * L / 2.0, rho_wall=rho_ext,
-                    steps=30000, rho_liquid=rl, rho_vapour=rv, rho_ext=rho_ext, rho_ref=rho_ext,
-                    shape="bubble", radius=30.0, noise_amp=1e-4, seed=4, shear_rate=shear_rate)
+                    steps=30000, rho_liquid=rl, rho_vapour=rv, rho_ext=rho_ext,
+                    rho_ref=storage_reference(rv, rho_ext), shape="bubble", radius=30.0, noise_amp=1e-4, seed=4, shear_rate=shear_rate)
 
 
 SHEAR_RATES = (1e-5, 5e-5, 1e-4, 5e-4)
@@ -240,6 +247,7 @@ def batched_sweep(n: int = 32, seed: int = 5) -> List[Workload]:
         out.append(Workload("batch_%02d" % r, L, L, T=T, a=a, b=b, kappa=1.0, tau=0.7,
                             bc_y=1 if gamma > 0 else 0, u_wall=gamma * L / 2.0,
                             rho_wall=rho_ext, steps=10000, rho_liquid=rl, rho_vapour=rv,
-                            rho_ext=rho_ext, rho_ref=rho_ext, shape="bubble", radius=R,
+                            rho_ext=rho_ext, rho_ref=storage_reference(rv, rho_ext),
+                            shape="bubble", radius=R,
                             noise_amp=1e-4, seed=nseed, shear_rate=gamma))
     return out

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ECFL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_DEV = 0, 1
 PERIODIC, SHEAR_WALLS = 0, 1
+ROUND_STOCHASTIC, ROUND_NEAREST = 0, 1
 
 
 class LbmError(RuntimeError):
@@ -41,6 +42,7 @@ class CParams(ctypes.Structure):
         ("bc_y", ctypes.c_int32),
         ("u_wall", ctypes.c_double), ("rho_wall", ctypes.c_double),
         ("clamp_radius", ctypes.c_double), ("clamp_rho", ctypes.c_double),
+        ("rounding", ctypes.c_int32),
     ]
 
 
@@ -72,6 +74,7 @@ class Params:
     rho_wall: float = 1.0
     clamp_radius: float = 0.0
     clamp_rho: float = 1.0
+    rounding: int = ROUND_STOCHASTIC
 
     def c(self) -> CParams:
         return CParams(*[getattr(self, f.name) for f in fields(self)])

@@ -27,6 +27,21 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_binding_struct_matches_header():
+    """The ctypes mirror of lbm_params has the header's fields, in order and
+    with the same C types."""
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{(.*?)\} lbm_params;", src, flags=re.S).group(1)
+    fields = []
+    for ctype, names in re.findall(r"(int32_t|double)\s+([^;]+);", body):
+        fields += [(n.strip(), ctype) for n in names.split(",")]
+    ct = {"int32_t": "c_int", "double": "c_double"}
+    got = [(n, t.__name__) for n, t in lbm.CParams._fields_]
+    assert got == [(n, ct[t]) for n, t in fields]
+    assert [f for f, _ in got] == [f.name for f in lbm.fields(lbm.Params)]
+
+
 def test_version_and_error_strings():
     assert "gfx950" in lbm.version()
 
@@ -44,6 +59,7 @@ def test_validate_accepts_paper_parameters():
     ("dt", 0.45, lbm.LBM_ECFL), ("Lx", 0, lbm.LBM_EINVAL), ("tau", 0.0, lbm.LBM_EINVAL),
     ("T", -1.0, lbm.LBM_EINVAL), ("scheme", 3, lbm.LBM_EINVAL), ("precision", 2, lbm.LBM_EINVAL),
     ("kappa", -1.0, lbm.LBM_EINVAL), ("ds", float("nan"), lbm.LBM_EINVAL), ("bc_y", 2, lbm.LBM_EINVAL),
+    ("rounding", 2, lbm.LBM_EINVAL),
 ])
 def test_validate_rejects(field, value, status):
     p = base()
