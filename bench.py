@@ -139,6 +139,10 @@ def main():
                     help="fixed launch shape ROWS,WAVES (rows per wavefront, wavefronts per workgroup) of the FP32 "
                          "stepper instead of the autotuner's")
     ap.add_argument("--launch64", default=None, help="the same for the FP64 stepper (WAVES at most 2)")
+    ap.add_argument("--regularize", action="store_true",
+                    help="regularized collision (Eq. ereg) instead of plain BGK; not the headline")
+    ap.add_argument("--scheme", type=int, default=2, choices=(1, 2),
+                    help="advection scheme: 2 = CTU2 (the headline), 1 = CTU1")
     ap.add_argument("--batched", action="store_true",
                     help="instead of the 6144^2 lattice: the 32-run sweep of uneven lattices in one batched, "
                          "graph-captured launch per step against the same runs stepped one after another")
@@ -170,6 +174,8 @@ def main():
     fixed = {"f32": tuple(int(v) for v in args.launch.split(",")) if args.launch else None,
              "f64": tuple(int(v) for v in args.launch64.split(",")) if args.launch64 else None}
     w = I.large_lattice(args.L)
+    w.regularize = 1 if args.regularize else 0
+    w.scheme = args.scheme
     rho, ux, uy = w.fields()
     nodes = w.Lx * w.Ly
     results = {}
@@ -230,11 +236,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "Lx": w.Lx, "Ly": w.Ly, "T_over_Tc": w.T, "rho_ext": round(w.rho_ext, 6),
-                   "bubble_radius": w.radius, "tau": w.tau, "kappa": w.kappa, "scheme": "CTU2",
+                   "bubble_radius": w.radius, "tau": w.tau, "kappa": w.kappa, "scheme": "CTU%d" % w.scheme,
+                   "regularize": w.regularize,
                    "storage": "FP32 f - w rho_ref", "rho_ref": round(w.rho_ref, 6), "launch": list(f32["launch"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic("step_fp32dev_ctu2_%d" % w.Lx)},
+                     "traffic": measured_traffic("step_fp32dev_ctu%d%s_%d" % (w.scheme, "_reg" if w.regularize else "", w.Lx))},
     }
     if "f64" in results:
         f64 = results["f64"]

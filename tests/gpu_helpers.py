@@ -36,3 +36,26 @@ def field_errors(rho, ux, uy, rho_ref, ux_ref, uy_ref):
         "rho_max": float(drho.max()), "rho_rms": float(np.sqrt(np.mean(drho ** 2))),
         "u_max": float(du.max() / umax), "u_rms": float(np.sqrt(np.mean(du ** 2)) / umax),
     }
+
+
+def box_rows(box, Ly, walls):
+    """Rows [r0, r1) of the cut for box (j0, j1, i0, i1): four rows of margin
+    (the reach of one step), wrapped periodically, or clipped at the walls."""
+    j0, j1 = box[0], box[1]
+    if walls:
+        r0, r1 = max(j0 - 4, 0), min(j1 + 4, Ly)
+        assert (r0 == 0 or r0 == j0 - 4) and (r1 == Ly or r1 == j1 + 4)
+        return r0, r1
+    return j0 - 4, j1 + 4
+
+
+def oracle_box_step(op, fcut, box, r0, Ly, walls):
+    """The oracle's step of box (j0, j1, i0, i1) from a cut of the input state
+    (rows [r0, r0 + fcut.shape[1]), columns [i0 - 4, i1 + 4), wrapped): the cut
+    is stepped as a small lattice, periodic, or with walls when it reaches a
+    wall row (its own wall on the far side lies out of the step's reach)."""
+    j0, j1, i0, i1 = box
+    q = o.Params(**{k: getattr(op, k) for k in op.__dataclass_fields__})
+    q.Lx, q.Ly = fcut.shape[2], fcut.shape[1]
+    q.bc_y = 1 if walls and (r0 == 0 or r0 + fcut.shape[1] == Ly) else 0
+    return o.step_region(q, np.ascontiguousarray(fcut), 4, 4 + (i1 - i0), j0 - r0, j1 - r0)

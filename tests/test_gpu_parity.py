@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle as o
-from gpu_helpers import field_errors, oracle_params, random_state, rel_err
+from gpu_helpers import box_rows, field_errors, oracle_box_step, oracle_params, random_state, rel_err
 from paper_1802_01272_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -446,3 +446,81 @@ def test_fp32dev_ten_thousand_steps_against_oracle():
     assert e["rho_max"] < 1e-5 and e["u_max"] < 1e-5
     e = errs[lbm.ROUND_NEAREST]
     assert e["rho_max"] < 5e-5 and e["u_max"] < 1e-4
+
+
+# ------------------------------------------------- full-size sampled parity
+
+def sampled_regions_step(p, rho, ux, uy, launch, boxes):
+    """One step of a full-size run in the given launch shape; for each box
+    (j0, j1, i0, i1) the GPU output is compared with the oracle's step of a
+    cut of the GPU's own input state around the box (gpu_helpers.box_rows,
+    oracle_box_step).  Returns the largest error relative to max |f| of each box."""
+    import torch
+    run = lbm.Run(p, rho, ux, uy)
+    run.set_launch(*launch)
+    Ly, Lx = p.Ly, p.Lx
+    cuts = []
+    fin = run.get_f_device()
+    for box in boxes:
+        r0, r1 = box_rows(box, Ly, p.bc_y)
+        cols = torch.arange(box[2] - 4, box[3] + 4, device="cuda") % Lx
+        rows = torch.arange(r0, r1, device="cuda") % Ly
+        cuts.append((r0, fin.index_select(1, rows).index_select(2, cols).cpu().numpy()))
+    del fin
+    torch.cuda.synchronize()
+    run.step(1)
+    fout = run.get_f_device()
+    errs = []
+    op = oracle_params(p)
+    for box, (r0, fcut) in zip(boxes, cuts):
+        j0, j1, i0, i1 = box
+        got = fout[:, j0:j1, :].index_select(2, torch.arange(i0, i1, device="cuda") % Lx).cpu().numpy()
+        errs.append(rel_err(got, oracle_box_step(op, fcut, box, r0, Ly, p.bc_y)))
+    run.close()
+    return errs
+
+
+def large_boxes(L, strip=56, rows=168):
+    c = L // 2
+    last_strip = (L // strip) * strip
+    last_chunk = (L // rows) * rows
+    return [
+        (0, 10, 0, 10),                                  # corner: periodic wrap in x and y
+        (L - 10, L, L - 10, L),                          # opposite corner, ragged last strip and chunk
+        (c - 64, c - 52, c - 6, c + 6),                  # bubble interface (radius 60)
+        (c - 6, c + 6, c + 55, c + 67),
+        (rows - 6, rows + 6, strip - 6, strip + 6),      # chunk and strip boundaries
+        (5 * rows - 5, 5 * rows + 7, 7 * strip - 7, 7 * strip + 5),
+        (last_chunk - 6, last_chunk + 6, last_strip - 6, last_strip + 6),
+    ]
+
+
+@pytest.mark.parametrize("precision,launch", [(1, (168, 1)), (0, (168, 2))])
+def test_full_size_6144_sampled_against_oracle(precision, launch):
+    """The 6144 x 6144 benchmark workload (bubble of radius 60, T = 0.95) in
+    the launch shapes the benchmark times: one step, seven sampled boxes
+    (wrapped corners, the bubble interface, strip and chunk boundaries, the
+    ragged last strip and chunk) against the oracle."""
+    w = I.large_lattice(6144)
+    rho, ux, uy = w.fields()
+    p = lbm.Params.from_workload(w, precision=precision)
+    errs = sampled_regions_step(p, rho, ux, uy, launch, large_boxes(6144))
+    print("6144^2 precision %d launch %s: box errors" % (precision, launch), ["%.1e" % e for e in errs])
+    assert max(errs) < (F64_STEP if precision == 0 else F32_STEP)
+
+
+def test_full_size_2048_sheared_sampled_against_oracle():
+    """The 2048 x 2048 sheared workload (walls moving at -+u_w, shear rate
+    1e-4, noise, FP32) in its default launch shape: boxes at both walls and
+    in the interior against the oracle."""
+    w = I.sheared_bubble(1e-4, 2048)
+    rho, ux, uy = w.fields()
+    p = lbm.Params.from_workload(w, precision=lbm.FP32_DEV)
+    boxes = [(0, 8, 0, 10), (2040, 2048, 2038, 2048), (0, 8, 1000, 1012), (2040, 2048, 55, 67),
+             (1000, 1012, 1020, 1032), (990, 1002, 1020 + 30, 1032 + 30)]
+    run = lbm.Run(p, rho, ux, uy)
+    launch = tuple(run.get_launch())
+    run.close()
+    errs = sampled_regions_step(p, rho, ux, uy, launch, boxes)
+    print("2048^2 sheared launch %s: box errors" % (launch,), ["%.1e" % e for e in errs])
+    assert max(errs) < F32_STEP

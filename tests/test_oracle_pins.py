@@ -591,3 +591,27 @@ def test_flat_interface_coexistence_converges_to_maxwell():
     (l1, v1), (l4, v4) = errs
     assert l1 < 0.012 and v1 < 0.10
     assert l4 < l1 / 2 and v4 < v1 / 2
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+def test_cut_box_step_equals_whole_step(walls):
+    """The full-size GPU tests compare sampled boxes with the oracle's step of
+    a cut around each box (four nodes of margin, the reach of one step;
+    periodic, or with walls where the cut reaches a wall): on a lattice the
+    oracle can step whole, every such cut reproduces the whole step on its
+    box."""
+    from gpu_helpers import box_rows, oracle_box_step
+    Lx, Ly = 40, 36
+    p = o.Params(Lx=Lx, Ly=Ly, T=0.93, kappa=0.8, tau=0.7, scheme=2, bc_y=walls,
+                 u_wall=0.04 if walls else 0.0, rho_wall=1.25)
+    rng = np.random.Generator(np.random.PCG64(12))
+    rho = 1.2 + 0.15 * rng.uniform(-1, 1, (Ly, Lx))
+    f = o.init(p, rho, 0.05 * rng.standard_normal((Ly, Lx)), 0.05 * rng.standard_normal((Ly, Lx)))
+    f = np.ascontiguousarray(f * (1.0 + 0.03 * rng.standard_normal(f.shape)))
+    whole = o.step(p, f)
+    for box in [(0, 6, 0, 7), (Ly - 6, Ly, Lx - 7, Lx), (10, 18, 15, 25), (3, 9, 36, 40)]:
+        j0, j1, i0, i1 = box
+        r0, r1 = box_rows(box, Ly, walls)
+        fcut = f[:, np.arange(r0, r1) % Ly][:, :, np.arange(i0 - 4, i1 + 4) % Lx]
+        got = oracle_box_step(p, fcut, box, r0, Ly, walls)
+        np.testing.assert_allclose(got, whole[:, j0:j1, i0:i1], rtol=0, atol=1e-14)
