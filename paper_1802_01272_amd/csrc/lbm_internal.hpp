@@ -48,10 +48,9 @@ constexpr size_t STEP_LDS_PER_WAVE = (size_t)PENDING_ROWS * 16 * WAVE * sizeof(d
 // read by the kernels through uniform (scalar) loads.
 template <typename R>
 struct StepCoef {
-    // advection, indexed by the magnitude class m of a velocity component
-    // (0: |xi| = QS, 1: |xi| = QL); nu = dt/ds.  CTU1 weights in FP64, the
-    // CTU2 blend weights in the storage precision R.
-    double nu_xi[2];  // nu |xi|
+    // advection, in the storage precision R, indexed by the magnitude class m
+    // of a velocity component (0: |xi| = QS, 1: |xi| = QL); nu = dt/ds
+    R nu_xi[2];    // nu |xi|                            (CTU1 weights)
     // CTU2: the limited corrections are kept unscaled, X' = S^x / k2[mx] and
     // Y' = S^y / k2[my] with k2 = |xi| (1 - nu |xi|); the scales are folded
     // into the blend weights of their differences, indexed [mx][my]:

@@ -38,12 +38,13 @@
 //    advective increment A_k(f) - f is formed from upwind differences, so it
 //    is exactly zero on a constant field in any precision.  Node-local
 //    arithmetic (moments, stencils, collision and force) is FP64 in both
-//    storage modes.  With FP32 storage, every rounding that repeats identically
+//    storage modes.  With FP32 storage, a rounding that repeats identically
 //    from step to step where the flow is nearly steady adds up coherently, so
-//    the FP32 path keeps only roundings that do not: the upwind differences
-//    and the CTU2 corrections are FP32, the CTU1 sum and the advected value
-//    f + (A f - f) are FP64 (exact from the FP32 operands), and the new
-//    deviation is rounded to FP32 stochastically (unbiased, seeded per step).
+//    the FP32 path avoids such roundings: the CTU1 weights are only nu |xi_x|
+//    and nu |xi_y| (a weight set that stays consistent when rounded), the
+//    advected value f + (A f - f) is formed in FP64 (exact from the FP32
+//    operands), and the new deviation is rounded to FP32 stochastically
+//    (unbiased, seeded per step).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -181,6 +182,17 @@ __device__ __forceinline__ uint32_t step_seed(uint32_t* seq, int cur, bool owner
     return mix32(n);
 }
 
+// CTU1 part b D2 + a (Dc + b (Du - Dc)) of the advective increment; with
+// FP64 storage f is folded in (the caller then adds only the corrections)
+__device__ __forceinline__ float ctu1_part(float, float D2, float Dc, float Du, float a, float b)
+{
+    return a * (Dc + b * (Du - Dc)) + b * D2;
+}
+__device__ __forceinline__ double ctu1_part(double f, double D2, double Dc, double Du, double a, double b)
+{
+    return __builtin_fma(b, D2, f) + a * __builtin_fma(b, Du - Dc, Dc);
+}
+
 // minmod(a, b) = median(a, b, 0): 0 when the signs differ, else the smaller one
 __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 __device__ __forceinline__ double minmod(double a, double b) { return fmax(fmin(a, b), fmin(fmax(a, b), 0.0)); }
@@ -257,10 +269,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     // collision starts from it unrounded.
     R B[4][16];
     // carries per velocity: the upwind x-difference D1 of the row the CTU1
-    // part reuses (FP64, exact from the storage precision), and for CTU2 Y'
-    // at row a and dX = X'_{i+1} - X'_i at row a-1 (s_y > 0) or a (s_y < 0)
-    N cD1[16];
-    R cY[16], cdX[16];
+    // part reuses, and for CTU2 Y' at row a and dX = X'_{i+1} - X'_i at row
+    // a-1 (s_y > 0) or a (s_y < 0)
+    R cD1[16], cY[16], cdX[16];
     // per-row stencil rings (same indexing by phase): advected density
     // deviation sums and their x-sums (row a), Laplacian rows and their
     // x-differences and x-sums (row a-1), pending 24-neighbour gradient sums
@@ -273,10 +284,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         dsr[i] = hsr[i] = Lr[i] = dLr[i] = sLr[i] = ax[i] = ay[i] = N(0);
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        cD1[k] = N(0);
-        cY[k] = cdX[k] = R(0);
-    }
+    for (int k = 0; k < 16; ++k) cD1[k] = cY[k] = cdX[k] = R(0);
     {
         const uint32_t voff = row_voff(y0 - 4);
 #pragma unroll
@@ -321,23 +329,22 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             // advective increment A_k(f) - f from upwind differences (exact on
             // constants): with D1 = f(i - s_x) - f(i) on row a (Dc) and on the
             // row upwind in y (Du), and D2 = f(a - s_y) - f(a), the CTU1 part
-            // is b D2 + a (Dc + b (Du - Dc)), a = nu |xi_x|, b = nu |xi_y|.  It
-            // is summed in FP64 from the FP32 differences (in FP32 storage
-            // mode the roundings of an FP32 sum repeat step after step where
-            // the flow is nearly steady and add up); D1 of the row that is
-            // reused one row later is carried in cD1.  The CTU2 corrections,
-            // second differences of limited slopes, stay in the storage
-            // precision.
-            const N ax = C->nu_xi[MX], ay = C->nu_xi[MY];
-            N adv;        // f + CTU1 part
+            // is b D2 + a (Dc + b (Du - Dc)), a = nu |xi_x|, b = nu |xi_y|.
+            // With only the two weights a and b, D1 enters with weight exactly
+            // a where Du = Dc, in any precision (separately rounded FP32
+            // weights a - ab, ab and a break that identity, a bias that
+            // repeats step after step).  D1 of the row that is reused one row
+            // later is carried in cD1.
+            const R ax = C->nu_xi[MX], ay = C->nu_xi[MY];
+            R inc;        // CTU1 part (FP64 storage: f + CTU1 part)
             R corr = 0;   // CTU2 corrections
             if constexpr (SY > 0) {
                 const R rx = fj - from_left(fj);          // R^x at row a
                 const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
                 const R D1 = (SX > 0) ? -rx : rxu;
                 const R D2 = D2m[K];
-                const N Dc = (N)D1, Du = cD1[K];
-                adv = __builtin_fma(ay, (N)D2, (N)fj) + ax * __builtin_fma(ay, Du - Dc, Dc);
+                const R Dc = D1, Du = cD1[K];
+                inc = ctu1_part(fj, D2, Dc, Du, ax, ay);
                 cD1[K] = Dc;
                 if constexpr (SCHEME == 2) {
                     // X' at row a and its x-difference; dX of row a-1 is carried
@@ -357,8 +364,8 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R rxu = upwind_x<SX>(rx);
                 const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row a+1
                 const R D2 = fjp - fj;
-                const N Dc = cD1[K], Du = (N)D1p;
-                adv = __builtin_fma(ay, (N)D2, (N)fj) + ax * __builtin_fma(ay, Du - Dc, Dc);
+                const R Dc = cD1[K], Du = D1p;
+                inc = ctu1_part(fj, D2, Dc, Du, ax, ay);
                 cD1[K] = Du;
                 if constexpr (SCHEME == 2) {
                     // X' at row a+1 and its x-difference; dX of row a is carried
@@ -374,8 +381,10 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 }
             }
             // wall ghost rows are boundary values: they keep their state
-            // (row a as loaded; a select, not a branch)
-            fs[K] = ghost_a ? (N)fj : adv + (N)corr;
+            // (row a as loaded; a select, not a branch).  FP32: f + increment
+            // is formed in FP64, exact from the two FP32 operands.
+            if constexpr (sizeof(R) == 4) fs[K] = ghost_a ? (N)fj : (N)fj + (N)(inc + corr);
+            else fs[K] = ghost_a ? fj : inc + corr;
         });
 
         // --- regularization of the advected row (Eq. ereg): project onto the
