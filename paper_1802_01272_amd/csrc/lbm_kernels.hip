@@ -183,14 +183,18 @@ __device__ __forceinline__ uint32_t step_seed(uint32_t* seq, int cur, bool owner
 }
 
 // CTU1 part b D2 + a (Dc + b (Du - Dc)) of the advective increment; with
-// FP64 storage f is folded in (the caller then adds only the corrections)
+// FOLD (FP64 storage, no walls) f is folded in, and the caller then adds only
+// the corrections
+template <bool FOLD>
 __device__ __forceinline__ float ctu1_part(float, float D2, float Dc, float Du, float a, float b)
 {
     return a * (Dc + b * (Du - Dc)) + b * D2;
 }
+template <bool FOLD>
 __device__ __forceinline__ double ctu1_part(double f, double D2, double Dc, double Du, double a, double b)
 {
-    return __builtin_fma(b, D2, f) + a * __builtin_fma(b, Du - Dc, Dc);
+    if constexpr (FOLD) return __builtin_fma(b, D2, f) + a * __builtin_fma(b, Du - Dc, Dc);
+    else return a * __builtin_fma(b, Du - Dc, Dc) + b * D2;
 }
 
 // minmod(a, b) = median(a, b, 0): 0 when the signs differ, else the smaller one
@@ -306,6 +310,11 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         const int a = r - 2;
         const int o = a - 2;
         const bool ghost_a = WALLS && (a < 0 || a >= Ly);
+        // wall ghost rows are boundary values that keep their state: the
+        // increment is multiplied by keep = 0 there (a select would let the
+        // compiler branch around each velocity's advection)
+        const N keep = ghost_a ? 0.0 : 1.0;
+        constexpr bool FOLD = sizeof(R) == 8 && !WALLS;
         // Row a-1 is only needed through D2 = f(a-1) - f(a) of the velocities
         // with s_y > 0: form those, then load row r+1 into its slot B[iM1]
         // before any store of this row (loads and stores share one in-order
@@ -336,7 +345,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             // repeats step after step).  D1 of the row that is reused one row
             // later is carried in cD1.
             const R ax = C->nu_xi[MX], ay = C->nu_xi[MY];
-            R inc;        // CTU1 part (FP64 storage: f + CTU1 part)
+            R inc;        // CTU1 part (FOLD: f + CTU1 part)
             R corr = 0;   // CTU2 corrections
             if constexpr (SY > 0) {
                 const R rx = fj - from_left(fj);          // R^x at row a
@@ -344,7 +353,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R D1 = (SX > 0) ? -rx : rxu;
                 const R D2 = D2m[K];
                 const R Dc = D1, Du = cD1[K];
-                inc = ctu1_part(fj, D2, Dc, Du, ax, ay);
+                inc = ctu1_part<FOLD>(fj, D2, Dc, Du, ax, ay);
                 cD1[K] = Dc;
                 if constexpr (SCHEME == 2) {
                     // X' at row a and its x-difference; dX of row a-1 is carried
@@ -365,7 +374,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row a+1
                 const R D2 = fjp - fj;
                 const R Dc = cD1[K], Du = D1p;
-                inc = ctu1_part(fj, D2, Dc, Du, ax, ay);
+                inc = ctu1_part<FOLD>(fj, D2, Dc, Du, ax, ay);
                 cD1[K] = Du;
                 if constexpr (SCHEME == 2) {
                     // X' at row a+1 and its x-difference; dX of row a is carried
@@ -380,11 +389,11 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     cY[K] = Y1;
                 }
             }
-            // wall ghost rows are boundary values: they keep their state
-            // (row a as loaded; a select, not a branch).  FP32: f + increment
-            // is formed in FP64, exact from the two FP32 operands.
-            if constexpr (sizeof(R) == 4) fs[K] = ghost_a ? (N)fj : (N)fj + (N)(inc + corr);
-            else fs[K] = ghost_a ? fj : inc + corr;
+            // f + increment in FP64 (FP32 storage: exact from the two FP32
+            // operands)
+            if constexpr (FOLD) fs[K] = inc + corr;
+            else if constexpr (WALLS) fs[K] = __builtin_fma(keep, (N)(inc + corr), (N)fj);
+            else fs[K] = (N)fj + (N)(inc + corr);
         });
 
         // --- regularization of the advected row (Eq. ereg): project onto the
