@@ -62,8 +62,11 @@ enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_NEAREST = 1 }; /* FP32 storage roundi
 
 /* Parameters of one run.  Names follow the paper (Sec. II and III). */
 typedef struct {
-    int32_t Lx, Ly;       /* lattice nodes along x and y, each >= 1, and
-                             Lx * Ly <= 2^26 (8192 x 8192)                     */
+    int32_t Lx, Ly;       /* lattice nodes along x and y, each >= 1; Lx * Ly
+                             (Lx * (Ly + 2) with walls) at most 2^26 (8192 x
+                             8192) with FP32 storage, at most 2^26 - 1 with
+                             FP64 storage (eight FP64 planes must span fewer
+                             than 2^32 bytes)                                  */
     double ds, dt;        /* lattice spacing and time step; CFL of Sec. II C 1:
                              dt * sqrt(3 + sqrt 6) <= ds                       */
     double tau;           /* BGK relaxation time, > 0 (Eq. eBGK)                */

@@ -59,9 +59,16 @@ lbm_status validate(const lbm_params* p)
 {
     if (!p) return fail(LBM_EINVAL, "null parameters");
     if (p->Lx < 1 || p->Ly < 1) return fail(LBM_EINVAL, "Lx and Ly must be >= 1");
-    // eight FP64 distribution planes must fit in 4 GiB (32-bit buffer offsets)
-    if ((int64_t)p->Lx * ((int64_t)p->Ly + (p->bc_y == LBM_SHEAR_WALLS ? 2 : 0)) > (int64_t)1 << 26)
-        return fail(LBM_EINVAL, "Lx * Ly (Lx * (Ly + 2) with walls) must not exceed 2^26 nodes");
+    // one buffer descriptor spans eight distribution planes: at most 2^26
+    // nodes per plane (32-bit buffer offsets), and the eight planes must end
+    // below the descriptor's 2^32 - 1 byte range (FP64: fewer than 2^26 nodes)
+    {
+        const int64_t plane = (int64_t)p->Lx * ((int64_t)p->Ly + (p->bc_y == LBM_SHEAR_WALLS ? 2 : 0));
+        const int64_t sb = (p->precision == LBM_FP32_DEV) ? 4 : 8;
+        if (plane > (int64_t)1 << 26 || 8 * plane * sb > ((int64_t)1 << 32) - 1)
+            return fail(LBM_EINVAL, "Lx * Ly (Lx * (Ly + 2) with walls) must not exceed 2^26 nodes with FP32 "
+                                    "storage and 2^26 - 1 with FP64 storage");
+    }
     const double vals[] = {p->ds, p->dt, p->tau, p->T, p->a, p->b, p->kappa, p->rho_ref, p->u_wall, p->rho_wall,
                            p->clamp_radius, p->clamp_rho};
     for (double v : vals)

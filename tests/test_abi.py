@@ -85,3 +85,25 @@ def test_fp32_workspace_is_half_of_fp64():
     p.precision = lbm.FP32_DEV
     b = lbm.workspace_bytes(p)
     assert abs((a - b) - 2 * 16 * 1024 * 1024 * 4) < 1 << 20
+
+
+def test_size_limit_is_two_to_the_26_nodes():
+    """A buffer descriptor spans eight distribution planes: with FP32 storage
+    8192 x 8192 = 2^26 nodes is accepted and one row more is refused; with
+    FP64 storage eight planes of 2^26 nodes would reach byte 2^32, one past
+    the descriptor's range, so the limit is 2^26 - 1 (with walls, the two
+    ghost rows count)."""
+    p = lbm.Params(Lx=8192, Ly=8192, precision=lbm.FP32_DEV)
+    assert lbm.validate(p) == lbm.LBM_OK
+    p.Ly = 8193
+    assert lbm.validate(p) == lbm.LBM_EINVAL
+    p = lbm.Params(Lx=8192, Ly=8190, bc_y=lbm.SHEAR_WALLS, precision=lbm.FP32_DEV)
+    assert lbm.validate(p) == lbm.LBM_OK
+    p.Ly = 8191
+    assert lbm.validate(p) == lbm.LBM_EINVAL
+    p = lbm.Params(Lx=8192, Ly=8192, precision=lbm.FP64)
+    assert lbm.validate(p) == lbm.LBM_EINVAL
+    p.Ly = 8191
+    assert lbm.validate(p) == lbm.LBM_OK
+    p = lbm.Params(Lx=8191, Ly=8193, precision=lbm.FP64)    # 2^26 - 1 nodes
+    assert lbm.validate(p) == lbm.LBM_OK

@@ -524,3 +524,28 @@ def test_full_size_2048_sheared_sampled_against_oracle():
     errs = sampled_regions_step(p, rho, ux, uy, launch, boxes)
     print("2048^2 sheared launch %s: box errors" % (launch,), ["%.1e" % e for e in errs])
     assert max(errs) < F32_STEP
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_maximum_size_8192_sampled_against_oracle(precision):
+    """The largest lattices a run accepts, 8192 x 8192 = 2^26 nodes with FP32
+    storage and 8192 x 8191 with FP64 storage (eight FP64 planes must span
+    fewer than 2^32 bytes, the range of one buffer descriptor), with the
+    bubble workload's fluid: one step in the default launch shape, sampled
+    boxes (wrapped corners, the ragged last strip of 16 columns, the bubble
+    interface) against the oracle.  At 8192 x 8192 in FP64 the last value of
+    planes 7 and 15 would lie outside the descriptor's range."""
+    w = I.quiescent_bubble(8192, radius=60.0)
+    if precision == 0:
+        w = w.with_size(8192, 8191)
+    rho, ux, uy = w.fields()
+    p = lbm.Params.from_workload(w, precision=precision)
+    run = lbm.Run(p, 1.0, 0.0, 0.0)
+    launch = tuple(run.get_launch())
+    run.close()
+    c = 4096
+    Ly = w.Ly
+    boxes = [(0, 8, 0, 8), (Ly - 8, Ly, 8180, 8192), (c - 66, c - 56, c - 5, c + 5), (2000, 2010, 8170, 8186)]
+    errs = sampled_regions_step(p, rho, ux, uy, launch, boxes)
+    print("8192^2 precision %d launch %s: box errors" % (precision, launch), ["%.1e" % e for e in errs])
+    assert max(errs) < (F64_STEP if precision == 0 else F32_STEP)
