@@ -549,3 +549,23 @@ def test_maximum_size_8192_sampled_against_oracle(precision):
     errs = sampled_regions_step(p, rho, ux, uy, launch, boxes)
     print("8192^2 precision %d launch %s: box errors" % (precision, launch), ["%.1e" % e for e in errs])
     assert max(errs) < (F64_STEP if precision == 0 else F32_STEP)
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("dt_case", ["cfl", "small"])
+def test_degenerate_time_steps(scheme, bc, dt_case):
+    """Degenerate Courant numbers, FP64, 20 steps against the oracle: dt at
+    the CFL limit of Sec. II C 1 (nu |xi| = 1 for the fast components, whose
+    upwind update is then an exact shift and whose limited corrections
+    vanish), and a small dt = 1/64 with tau = dt/2 + 0.01, close to the
+    vanishing viscosity T (tau - dt/2) of the split scheme."""
+    ql = (3 + 6 ** 0.5) ** 0.5
+    if dt_case == "cfl":
+        p = make_params(70, 45, scheme, 0, bc, dt=1.0 / ql)
+    else:
+        p = make_params(70, 45, scheme, 0, bc, dt=1.0 / 64, tau=1.0 / 128 + 0.01)
+    f = random_state(p, 150 + scheme + 2 * bc)
+    got = gpu_step_from(p, f, nsteps=20)
+    ref = o.run(oracle_params(p), f.copy(), 20)
+    assert rel_err(got, ref) < 1e-12
