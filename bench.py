@@ -136,8 +136,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true")
     ap.add_argument("--launch", default=None,
-                    help="fixed launch shape ROWS,WAVES (rows per wavefront, wavefronts per workgroup) of the FP32 "
-                         "stepper instead of the autotuner's")
+                    help="fixed launch shape ROWS,WAVES (rows per strip and workgroup; wavefronts per workgroup, "
+                         "or 0 for a pair of wavefronts per strip) of the FP32 stepper instead of the autotuner's")
     ap.add_argument("--launch64", default=None, help="the same for the FP64 stepper (WAVES at most 2)")
     ap.add_argument("--regularize", action="store_true",
                     help="regularized collision (Eq. ereg) instead of plain BGK; not the headline")

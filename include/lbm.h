@@ -59,6 +59,7 @@ typedef enum {
 enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };     /* storage precision               */
 enum { LBM_PERIODIC = 0, LBM_SHEAR_WALLS = 1 }; /* boundary in y                 */
 enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_NEAREST = 1 }; /* FP32 storage rounding */
+enum { LBM_PAIR = 0 };  /* waves_per_group of lbm_set_launch: see there          */
 
 /* Parameters of one run.  Names follow the paper (Sec. II and III). */
 typedef struct {
@@ -196,10 +197,15 @@ lbm_status lbm_set_f_device(lbm_run* run, const double* d_f, void* stream);
  * Returns LBM_ENONFINITE (with *out filled) when n_nonfinite > 0.  sync. */
 lbm_status lbm_reduce(lbm_run* run, double rho_threshold, lbm_stats* out, void* stream);
 
-/* Launch shape: rows of the lattice each wavefront advances (>= 1) and
- * wavefronts per workgroup (1 or 2: the step kernels keep 32 KiB of LDS per
- * wavefront; 4 is refused).  LBM_EINVAL otherwise, and the previous shape is
- * kept.  Defaults come from lbm_autotune or a built-in table. */
+/* Launch shape: rows of the lattice each strip of 56 columns advances per
+ * workgroup (>= 1), and waves_per_group: 1 or 2 wavefronts per workgroup,
+ * each marching its own strip (the step kernels keep 32 KiB of LDS per
+ * wavefront; 4 is refused), or LBM_PAIR (FP32 storage only): a workgroup of
+ * two wavefronts per strip, one advecting and one colliding, which share the
+ * advected rows through LDS (each role needs few enough registers for two
+ * wavefronts per SIMD).  LBM_EINVAL otherwise, and the previous shape is kept.
+ * Defaults come from lbm_autotune or a built-in table (FP32: LBM_PAIR with
+ * 32 rows). */
 lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per_group);
 lbm_status lbm_get_launch(const lbm_run* run, int32_t* rows_per_wave, int32_t* waves_per_group);
 

@@ -179,6 +179,9 @@ size_t run_bytes(const lbm_params* p)
 // per wavefront that minimise rounds x (rows + 5).
 Launch default_launch(const lbm_params* p)
 {
+    // FP32 storage: a pair of wavefronts per strip, short chunks (measured
+    // best at 32-40 rows on 6144^2)
+    if (p->precision == LBM_FP32_DEV) return Launch{32, LBM_PAIR};
     static int slots = 0;
     if (slots == 0) {
         int dev = 0, ncu = 0;
@@ -203,14 +206,19 @@ Launch default_launch(const lbm_params* p)
 }
 
 // LDS of a step workgroup: the kernels keep the advected rows that wait for
-// their collision there (32 KiB per wavefront); capped at 64 KiB per workgroup
+// their collision there (32 KiB per wavefront, or per pair); capped at 64 KiB
+// per workgroup.  The pair launch is built for FP32 storage only.
 constexpr size_t MAX_STEP_LDS = 65536;
 size_t step_lds_bytes(const lbm_params* p, int wpg)
 {
     (void)p;
-    return (size_t)wpg * STEP_LDS_PER_WAVE;
+    return wpg == LBM_PAIR ? PAIR_STEP_LDS : (size_t)wpg * STEP_LDS_PER_WAVE;
 }
-bool launch_fits(const lbm_params* p, int wpg) { return step_lds_bytes(p, wpg) <= MAX_STEP_LDS; }
+bool launch_fits(const lbm_params* p, int wpg)
+{
+    if (wpg == LBM_PAIR && p->precision != LBM_FP32_DEV) return false;
+    return step_lds_bytes(p, wpg) <= MAX_STEP_LDS;
+}
 
 std::mutex g_tune_mutex;
 // (Lx, Ly, precision, scheme, regularize, bc_y)
@@ -658,10 +666,12 @@ lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per
 {
     if (!run) return fail(LBM_EINVAL, "null run");
     if (rows_per_wave < 1) return fail(LBM_EINVAL, "rows_per_wave must be >= 1");
-    if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
-        return fail(LBM_EINVAL, "waves_per_group must be 1, 2 or 4");
+    if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4 && waves_per_group != LBM_PAIR)
+        return fail(LBM_EINVAL, "waves_per_group must be 1, 2, 4 or LBM_PAIR");
     if (!launch_fits(&run->p, waves_per_group))
-        return fail(LBM_EINVAL, "waves_per_group too large for the LDS of the step kernel (at most 2)");
+        return fail(LBM_EINVAL, waves_per_group == LBM_PAIR
+                                    ? "LBM_PAIR launches need FP32 storage"
+                                    : "waves_per_group too large for the LDS of the step kernel (at most 2)");
     run->launch = Launch{rows_per_wave, waves_per_group};
     return LBM_OK;
 }
@@ -703,13 +713,13 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_ws, size_t ws_bytes, void* 
         HIP_TRY(hipStreamSynchronize(s), "autotune init");
     }
     // fixed candidates plus the default shape's rows and its neighbours
-    std::vector<int> rows_c = {8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+    std::vector<int> rows_c = {8, 16, 24, 32, 40, 48, 64, 96, 128, 192, 256, 384, 512};
     {
         const int d = default_launch(p).rows_per_wave;
         for (int r : {d - 16, d - 8, d, d + 8, d + 16})
             if (r >= 8 && std::find(rows_c.begin(), rows_c.end(), r) == rows_c.end()) rows_c.push_back(r);
     }
-    const int wpg_c[] = {1, 2, 4};
+    const int wpg_c[] = {1, 2, 4, LBM_PAIR};
     double best = 1e300;
     Launch bl = default_launch(p);
     for (int rows : rows_c) {

@@ -42,6 +42,9 @@ constexpr int STRIP = WAVE - 2 * HALO;
 // LDS: 32 KiB per wavefront.
 constexpr int PENDING_ROWS = 4;
 constexpr size_t STEP_LDS_PER_WAVE = (size_t)PENDING_ROWS * 16 * WAVE * sizeof(double);
+// a pair of wavefronts per strip (advecting and colliding) shares one such
+// ring and a ring of the advected rows' densities
+constexpr size_t PAIR_STEP_LDS = STEP_LDS_PER_WAVE + (size_t)PENDING_ROWS * WAVE * sizeof(double);
 
 // ---------------------------------------------------------------------------
 // Per-run coefficients, prepared on the host in the storage precision R and

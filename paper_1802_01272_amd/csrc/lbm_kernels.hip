@@ -226,13 +226,19 @@ template <typename R> struct G5W {
 // holds f^n at rows a-1, a, a+1 and the new row a+2; the ring S holds the
 // advected rows a-2, a-1 and a until row a-2 is collided.
 
-template <typename R, int SCHEME, bool REG, bool WALLS>
+// ROLE 0: one wavefront does the whole march.  ROLE 1 / ROLE 2: the advecting
+// and the colliding wavefront of a pair that shares the LDS ring of advected
+// rows (pend) and a ring of their densities (dsl); one barrier per row, the
+// collider one row behind the advector.
+template <typename R, int SCHEME, bool REG, bool WALLS, int ROLE = 0>
 __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restrict__ fout,
                                            const StepCoef<R>* __restrict__ C,
                                            const int Lx, const int Ly, const int64_t plane,
                                            const int strip, const int y0, const int y1,
-                                           double* __restrict__ pend, const uint32_t seed)
+                                           double* __restrict__ pend, const uint32_t seed,
+                                           double* __restrict__ dsl = nullptr)
 {
+    constexpr bool ADV = ROLE != 2, COL = ROLE != 1;
     using N = double;  // node-local arithmetic (moments, stencils, collision)
     const int lane = threadIdx.x & (WAVE - 1);
     int col = (strip * STRIP - HALO + lane) % Lx;
@@ -289,7 +295,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) cD1[k] = cY[k] = cdX[k] = R(0);
-    {
+    if constexpr (ADV) {
         const uint32_t voff = row_voff(y0 - 4);
 #pragma unroll
         for (int k = 0; k < 16; ++k) buf_load(B[0][k], src, k, voff, pbytes);
@@ -320,6 +326,8 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         // before any store of this row (loads and stores share one in-order
         // completion counter, so the next row's wait then never waits on
         // this row's stores).
+        N ds_r;
+        if constexpr (ADV) {
         R D2m[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -450,11 +458,21 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         }
 
         // --- advected density of row a and the force stencils (Eq. eder) -----
-        N ds_r = fs[0];
+        ds_r = fs[0];
 #pragma unroll
         for (int k = 1; k < 16; ++k) ds_r += fs[k];
 #pragma unroll
         for (int k = 0; k < 16; ++k) pend[(iN * 16 + k) * WAVE + lane] = fs[k];
+        if constexpr (ROLE == 1) {
+            dsl[iN * WAVE + lane] = ds_r;
+            __syncthreads();
+        }
+        }  // ADV
+        if constexpr (COL) {
+        if constexpr (ROLE == 2) {
+            __syncthreads();
+            ds_r = dsl[iN * WAVE + lane];
+        }
         const N rho_r = C->rho0 + ds_r;
         // p^i - p^w = rho T - rho T/(1 - b rho) + a rho^2 = rho^2 (a - b T/(1 - b rho))
         const N phi_r = rho_r * rho_r * (C->a_vdw - C->b_vdw * C->T * recip(1.0 - C->b_vdw * rho_r));
@@ -595,6 +613,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 }
             });
         }
+        }  // COL
     };
 
     // scheduling barriers keep the compiler from interleaving consecutive row
@@ -670,6 +689,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
     const int y1 = min(y0 + rows, Ly);
     const uint32_t seed = step_seed<R>(seq, cur, wave == 0);
     strip_step<R, SCHEME, REG, WALLS>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1, wave_lds(), seed);
+}
+
+// A pair of wavefronts per strip (workgroup of 128 lanes): wavefront 0
+// advects, wavefront 1 collides and stores.  Each role needs only its own
+// registers, so two wavefronts fit one SIMD.
+template <typename R, int SCHEME, bool REG, bool WALLS>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void pair_step_kernel(
+    const R* __restrict__ fin, R* __restrict__ fout, const StepCoef<R>* __restrict__ coef,
+    uint32_t* __restrict__ seq, int cur, int Lx, int Ly, int64_t plane, int rows, int nstrips, int npairs)
+{
+    const int pair = __builtin_amdgcn_readfirstlane(xcd_logical_block(blockIdx.x, gridDim.x));
+    if (pair >= npairs) return;  // the whole workgroup leaves together
+    const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int chunk = pair / nstrips, strip = pair - chunk * nstrips;
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, Ly);
+    double* const pend = reinterpret_cast<double*>(step_lds);  // PAIR_STEP_LDS bytes
+    double* const dsl = pend + PENDING_ROWS * 16 * WAVE;
+    if (role == 0) {
+        strip_step<R, SCHEME, REG, WALLS, 1>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1, pend, 0u, dsl);
+    } else {
+        const uint32_t seed = step_seed<R>(seq, cur, pair == 0);
+        strip_step<R, SCHEME, REG, WALLS, 2>(fin, fout, coef, Lx, Ly, plane, strip, y0, y1, pend, seed, dsl);
+    }
 }
 
 template <typename R, int SCHEME, bool REG, bool WALLS>
@@ -861,14 +904,24 @@ int grid_for(int64_t n, int block)
 template <typename R>
 hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int walls, int wpg, hipStream_t s)
 {
+    // wpg = LBM_PAIR: one workgroup of two wavefronts per strip and chunk
+    // (FP32 storage); else wpg independent wavefronts per workgroup
+    const bool pair = wpg == LBM_PAIR;
+    if (pair && sizeof(R) != 4) return hipErrorInvalidValue;
+    if (pair) wpg = 1;
     const int nchunks = (rv.Ly + rv.rows - 1) / rv.rows;
-    const int nwaves = rv.nstrips * nchunks;
+    const int nwaves = rv.nstrips * nchunks;  // pairs with LBM_PAIR
     const int nblocks = (nwaves + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
     const size_t lds = wpg * STEP_LDS_PER_WAVE;
-#define LBM_LAUNCH(SC, RG, WL)                                                                                \
-    hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, lds, s, rv.f_in, rv.f_out, rv.coef, rv.seq, \
-                       rv.cur, rv.Lx, rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
+#define LBM_LAUNCH(SC, RG, WL)                                                                                 \
+    if (pair)                                                                                                  \
+        hipLaunchKernelGGL((pair_step_kernel<R, SC, RG, WL>), dim3(nwaves), dim3(2 * WAVE), PAIR_STEP_LDS, s, \
+                           rv.f_in, rv.f_out, rv.coef, rv.seq, rv.cur, rv.Lx, rv.Ly, rv.plane, rv.rows,      \
+                           rv.nstrips, nwaves);                                                               \
+    else                                                                                                       \
+        hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, lds, s, rv.f_in, rv.f_out, rv.coef,     \
+                           rv.seq, rv.cur, rv.Lx, rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
 #define LBM_LAUNCH_W(SC, RG)          \
     if (walls) LBM_LAUNCH(SC, RG, true); \
     else LBM_LAUNCH(SC, RG, false)

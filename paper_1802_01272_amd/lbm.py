@@ -21,6 +21,7 @@ LBM_OK, LBM_EINVAL, LBM_ECFL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTAT
 FP64, FP32_DEV = 0, 1
 PERIODIC, SHEAR_WALLS = 0, 1
 ROUND_STOCHASTIC, ROUND_NEAREST = 0, 1
+PAIR = 0  # waves_per_group of a launch shape: two wavefronts per strip (FP32 storage)
 
 
 class LbmError(RuntimeError):

@@ -200,7 +200,8 @@ def test_one_step_edge_sizes(Lx, Ly, bc):
 
 
 @pytest.mark.parametrize("precision,launch", [(0, (1, 1)), (0, (3, 2)), (0, (7, 2)), (0, (64, 1)), (0, (256, 2)),
-                                              (1, (1, 1)), (1, (7, 2)), (1, (33, 2)), (1, (168, 1))])
+                                              (1, (1, 1)), (1, (7, 2)), (1, (33, 2)), (1, (168, 1)),
+                                              (1, (1, 0)), (1, (7, 0)), (1, (32, 0)), (1, (200, 0))])
 def test_launch_shape_does_not_change_results(precision, launch):
     """Chunking rows differently changes nothing beyond rounding (a row's
     position in the unrolled row loop may round a multiply-add differently);
@@ -216,13 +217,22 @@ def test_launch_shape_does_not_change_results(precision, launch):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_rejects_four_waves_per_group(precision):
     """The step kernels hold 32 KiB of LDS per wavefront: four per workgroup
-    are refused with LBM_EINVAL and the previous shape is kept."""
+    are refused with LBM_EINVAL and the previous shape is kept; the pair
+    launch (one advecting and one colliding wavefront per strip) is for FP32
+    storage only."""
     run = lbm.Run(make_params(40, 20, precision=precision), 1.0, 0.0, 0.0)
     run.set_launch(16, 2)
     with pytest.raises(lbm.LbmError) as ei:
         run.set_launch(16, 4)
     assert ei.value.status == lbm.LBM_EINVAL
     assert tuple(run.get_launch()) == (16, 2)
+    if precision == 0:
+        with pytest.raises(lbm.LbmError):
+            run.set_launch(16, lbm.PAIR)
+        assert tuple(run.get_launch()) == (16, 2)
+    else:
+        run.set_launch(16, lbm.PAIR)
+        assert tuple(run.get_launch()) == (16, lbm.PAIR)
     run.close()
 
 
@@ -495,7 +505,7 @@ def large_boxes(L, strip=56, rows=168):
     ]
 
 
-@pytest.mark.parametrize("precision,launch", [(1, (168, 1)), (0, (168, 2))])
+@pytest.mark.parametrize("precision,launch", [(1, (32, 0)), (1, (168, 1)), (0, (168, 2))])
 def test_full_size_6144_sampled_against_oracle(precision, launch):
     """The 6144 x 6144 benchmark workload (bubble of radius 60, T = 0.95) in
     the launch shapes the benchmark times: one step, seven sampled boxes
