@@ -236,13 +236,15 @@ lbm_status lbm_batch_init(int32_t n, const lbm_params* params, void* d_ws, size_
  * one HIP graph on first use and replays it; 0 launches directly.  async. */
 lbm_status lbm_batch_step(lbm_batch* batch, int64_t nsteps, int32_t graph_steps, void* stream);
 
-/* Rows of each run that one wavefront advances (>= 1) for every run of the
- * batch; rebuilds the work list and drops a captured graph.  sync. */
+/* Rows of each run that one work item advances (>= 1) for every run of the
+ * batch; rebuilds the work list and drops a captured graph.  FP32 batches
+ * run a pair of wavefronts per work item (as LBM_PAIR), FP64 batches one
+ * wavefront.  sync. */
 lbm_status lbm_batch_set_launch(lbm_batch* batch, int32_t rows_per_wave, void* stream);
 
-/* Time candidate rows-per-wavefront values on the batch itself and keep the
+/* Time candidate rows-per-item values on the batch itself and keep the
  * fastest.  The trials advance every run: by (steps_per_trial + 1) steps per
- * candidate (8 candidates).  sync. */
+ * candidate (10 candidates).  sync. */
 lbm_status lbm_batch_autotune(lbm_batch* batch, int32_t steps_per_trial, void* stream,
                               int32_t* rows_per_wave);
 

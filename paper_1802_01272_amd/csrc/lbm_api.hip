@@ -831,7 +831,7 @@ lbm_status batch_launch(lbm_batch* b, hipStream_t s)
         if (b->precision == LBM_FP32_DEV)
             e = launch_batch_step<float>(static_cast<const BatchRun<float>*>(b->d_runs),
                                          static_cast<const StepCoef<float>*>(b->d_coefs), items, n, b->cur,
-                                         b->scheme, b->regularize, walls, 1, s);
+                                         b->scheme, b->regularize, walls, LBM_PAIR, s);
         else
             e = launch_batch_step<double>(static_cast<const BatchRun<double>*>(b->d_runs),
                                           static_cast<const StepCoef<double>*>(b->d_coefs), items, n, b->cur,
@@ -991,7 +991,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps_per_trial, void* strea
     if (!b || !rows_per_wave) return fail(LBM_EINVAL, "null argument");
     if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int rows_c[] = {16, 32, 48, 64, 96, 128, 192, 256};
+    const int rows_c[] = {16, 24, 32, 40, 48, 64, 96, 128, 192, 256};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "batch autotune");
     HIP_TRY(hipEventCreate(&e1), "batch autotune");

@@ -736,6 +736,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
                                       run.Lx, run.Ly, run.plane, it.strip, y0, y1, wave_lds(), seed);
 }
 
+// The batched launch with a pair of wavefronts per work item (FP32 storage).
+template <typename R, int SCHEME, bool REG, bool WALLS>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void batch_pair_step_kernel(
+    const BatchRun<R>* __restrict__ runs, const StepCoef<R>* __restrict__ coefs, const BatchItem* __restrict__ items,
+    int nitems, int cur)
+{
+    const int w = __builtin_amdgcn_readfirstlane(xcd_logical_block(blockIdx.x, gridDim.x));
+    if (w >= nitems) return;  // the whole workgroup leaves together
+    const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const BatchItem it = items[w];
+    const BatchRun<R> run = runs[it.run];
+    const int y0 = it.chunk * run.rows;
+    const int y1 = min(y0 + run.rows, run.Ly);
+    R* const fa = run.f[0];
+    R* const fb = run.f[1];
+    double* const pend = reinterpret_cast<double*>(step_lds);  // PAIR_STEP_LDS bytes
+    double* const dsl = pend + PENDING_ROWS * 16 * WAVE;
+    if (role == 0) {
+        strip_step<R, SCHEME, REG, WALLS, 1>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx, run.Ly,
+                                             run.plane, it.strip, y0, y1, pend, 0u, dsl);
+    } else {
+        const uint32_t seed = step_seed<R>(run.seq, cur, it.strip == 0 && it.chunk == 0);
+        strip_step<R, SCHEME, REG, WALLS, 2>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx, run.Ly,
+                                             run.plane, it.strip, y0, y1, pend, seed, dsl);
+    }
+}
+
 // ----------------------------------------------------------------------------
 // auxiliary kernels (all in FP64 arithmetic)
 
@@ -943,11 +970,19 @@ hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coe
                              hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
+    const bool pair = wpg == LBM_PAIR;
+    if (pair && sizeof(R) != 4) return hipErrorInvalidValue;
+    if (pair) wpg = 1;
     const int nblocks = (nitems + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
     const size_t lds = wpg * STEP_LDS_PER_WAVE;
-#define LBM_LAUNCH(SC, RG, WL) \
-    hipLaunchKernelGGL((batch_step_kernel<R, SC, RG, WL>), grid, block, lds, s, d_runs, d_coefs, d_items, nitems, cur)
+#define LBM_LAUNCH(SC, RG, WL)                                                                                  \
+    if (pair)                                                                                                   \
+        hipLaunchKernelGGL((batch_pair_step_kernel<R, SC, RG, WL>), dim3(nitems), dim3(2 * WAVE), PAIR_STEP_LDS, \
+                           s, d_runs, d_coefs, d_items, nitems, cur);                                           \
+    else                                                                                                        \
+        hipLaunchKernelGGL((batch_step_kernel<R, SC, RG, WL>), grid, block, lds, s, d_runs, d_coefs, d_items,   \
+                           nitems, cur)
 #define LBM_LAUNCH_W(SC, RG)          \
     if (walls) LBM_LAUNCH(SC, RG, true); \
     else LBM_LAUNCH(SC, RG, false)

@@ -361,8 +361,8 @@ class Batch:
         _check(LIB.lbm_batch_set_launch(self.handle, int(rows_per_wave), _stream_handle(self.torch, stream)))
 
     def autotune(self, steps_per_trial: int = 3, stream=None) -> int:
-        """Pick the rows per wavefront on the batch itself; advances every run
-        by 8 * (steps_per_trial + 1) steps."""
+        """Pick the rows per work item on the batch itself; advances every run
+        by 10 * (steps_per_trial + 1) steps."""
         rows = ctypes.c_int32()
         _check(LIB.lbm_batch_autotune(self.handle, int(steps_per_trial), _stream_handle(self.torch, stream),
                                       ctypes.byref(rows)))

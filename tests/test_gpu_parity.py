@@ -407,8 +407,8 @@ def test_batch_set_launch_and_autotune():
     for m, ref in zip(batch.runs, singles):
         assert np.array_equal(m.get_f(), ref)
     rows = batch.autotune(1)
-    assert rows in (16, 32, 48, 64, 96, 128, 192, 256)
-    assert all(m.step_count == 3 + 8 * 2 for m in batch.runs)
+    assert rows in (16, 24, 32, 40, 48, 64, 96, 128, 192, 256)
+    assert all(m.step_count == 3 + 10 * 2 for m in batch.runs)
     st = batch.runs[0].reduce(1.0)
     assert st["n_nonfinite"] == 0
 
