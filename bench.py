@@ -184,7 +184,7 @@ def main():
         if name == "f64" and args.fp32_only:
             continue
         p = lbm.Params.from_workload(w, precision=prec)
-        launch = fixed[name] if fixed[name] else (None if args.no_autotune else lbm.autotune(p, steps_per_trial=5))
+        launch = fixed[name] if fixed[name] else (None if args.no_autotune else lbm.autotune(p, steps_per_trial=10))
         run = lbm.Run(p, rho, ux, uy)
         if launch:
             run.set_launch(*launch)
