@@ -303,8 +303,11 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
 
     // COLL = false: the first eight rows of the march only fill the rings
     // (advection, density, stencil sums); nothing is collided or stored.
-    auto body = [&](auto ph, auto coll, const int t) {
+    // WORK = false: the row only loads (its advected row lies below any
+    // stencil of the chunk)
+    auto body = [&](auto ph, auto coll, const int t, auto work) {
         constexpr bool COLL = decltype(coll)::value;
+        constexpr bool WORK = decltype(work)::value;
         constexpr int P = decltype(ph)::value;
         constexpr int iN = P, iM1 = (P + 1) & 3, i0 = (P + 2) & 3, iP1 = (P + 3) & 3;
         R(&cur)[16] = B[iN];
@@ -327,7 +330,13 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         // completion counter, so the next row's wait then never waits on
         // this row's stores).
         N ds_r;
-        if constexpr (ADV) {
+        if constexpr (ADV && !WORK) {
+            const uint32_t nvoff = row_voff(r + 1);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) buf_load(fm1[k], src, k, nvoff, pbytes);
+            if constexpr (ROLE == 1) __syncthreads();
+        }
+        if constexpr (ADV && WORK) {
         R D2m[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -468,7 +477,10 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             __syncthreads();
         }
         }  // ADV
-        if constexpr (COL) {
+        if constexpr (COL && !WORK) {
+            if constexpr (ROLE == 2) __syncthreads();
+        }
+        if constexpr (COL && WORK) {
         if constexpr (ROLE == 2) {
             __syncthreads();
             ds_r = dsl[iN * WAVE + lane];
@@ -627,25 +639,32 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     int t0 = 0;
     if constexpr (PEEL) {
         t0 = 8;
-        for (int t = 0; t < 8; t += 4) {
-            body(std::integral_constant<int, 0>{}, Z{}, t);
-            __builtin_amdgcn_sched_barrier(0);
-            body(std::integral_constant<int, 1>{}, Z{}, t + 1);
-            __builtin_amdgcn_sched_barrier(0);
-            body(std::integral_constant<int, 2>{}, Z{}, t + 2);
-            __builtin_amdgcn_sched_barrier(0);
-            body(std::integral_constant<int, 3>{}, Z{}, t + 3);
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        // rows t = 0..2 only load: they would advect rows below y0 - 3, which
+        // no stencil of the chunk reaches, and row t = 3 forms afresh the
+        // carries that row t = 4 needs
+        body(std::integral_constant<int, 0>{}, Z{}, 0, Z{});
+        body(std::integral_constant<int, 1>{}, Z{}, 1, Z{});
+        body(std::integral_constant<int, 2>{}, Z{}, 2, Z{});
+        __builtin_amdgcn_sched_barrier(0);
+        body(std::integral_constant<int, 3>{}, Z{}, 3, O{});
+        __builtin_amdgcn_sched_barrier(0);
+        body(std::integral_constant<int, 0>{}, Z{}, 4, O{});
+        __builtin_amdgcn_sched_barrier(0);
+        body(std::integral_constant<int, 1>{}, Z{}, 5, O{});
+        __builtin_amdgcn_sched_barrier(0);
+        body(std::integral_constant<int, 2>{}, Z{}, 6, O{});
+        __builtin_amdgcn_sched_barrier(0);
+        body(std::integral_constant<int, 3>{}, Z{}, 7, O{});
+        __builtin_amdgcn_sched_barrier(0);
     }
     for (int t = t0; t < niter4; t += 4) {
-        body(std::integral_constant<int, 0>{}, O{}, t);
+        body(std::integral_constant<int, 0>{}, O{}, t, O{});
         __builtin_amdgcn_sched_barrier(0);
-        body(std::integral_constant<int, 1>{}, O{}, t + 1);
+        body(std::integral_constant<int, 1>{}, O{}, t + 1, O{});
         __builtin_amdgcn_sched_barrier(0);
-        body(std::integral_constant<int, 2>{}, O{}, t + 2);
+        body(std::integral_constant<int, 2>{}, O{}, t + 2, O{});
         __builtin_amdgcn_sched_barrier(0);
-        body(std::integral_constant<int, 3>{}, O{}, t + 3);
+        body(std::integral_constant<int, 3>{}, O{}, t + 3, O{});
         __builtin_amdgcn_sched_barrier(0);
     }
 }
