@@ -211,7 +211,10 @@ lbm_status lbm_get_launch(const lbm_run* run, int32_t* rows_per_wave, int32_t* w
 
 /* Time each candidate launch shape for a run with parameters p on a
  * synthetic state held in d_ws (>= lbm_workspace_bytes(p); its contents are
- * overwritten) and return the fastest.  sync. */
+ * overwritten) and return the fastest: rows per chunk from 8 to 512, and
+ * waves_per_group 1, 2 or (FP32 storage) LBM_PAIR; 2 + steps_per_trial steps
+ * per candidate.  Runs with p's shape created later in the process start
+ * with the result.  sync. */
 lbm_status lbm_autotune(const lbm_params* p, void* d_ws, size_t ws_bytes, void* stream,
                         int32_t steps_per_trial, int32_t* rows_per_wave, int32_t* waves_per_group);
 
