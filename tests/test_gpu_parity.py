@@ -190,13 +190,20 @@ def test_bubble_with_clamp_fp64_many_steps():
 @pytest.mark.parametrize("Lx,Ly", [(1, 1), (1, 6), (2, 3), (5, 1), (55, 4), (56, 2), (57, 3), (63, 5), (64, 3),
                                    (65, 7), (111, 2), (112, 5), (113, 1), (200, 1)])
 @pytest.mark.parametrize("bc", [0, 1])
-def test_one_step_edge_sizes(Lx, Ly, bc):
-    """Lattices narrower than a wavefront, ragged last strips, a single row or column."""
-    p = make_params(Lx, Ly, 2, 0, bc)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_one_step_edge_sizes(Lx, Ly, bc, precision):
+    """Lattices narrower than a wavefront, ragged last strips, a single row or
+    column; FP32 in its default launch (a pair of wavefronts per strip)."""
+    p = make_params(Lx, Ly, 2, 0, bc, precision=precision)
     f = random_state(p, 30 + Lx + Ly)
     got = gpu_step_from(p, f)
+    if precision:
+        run = lbm.Run(p, 1.0, 0.0, 0.0)
+        run.set_f(f)
+        f = run.get_f()   # the FP32-stored state the GPU stepped
+        run.close()
     ref = o.step(oracle_params(p), f)
-    assert rel_err(got, ref) < F64_STEP
+    assert rel_err(got, ref) < (F64_STEP if precision == 0 else F32_STEP)
 
 
 @pytest.mark.parametrize("precision,launch", [(0, (1, 1)), (0, (3, 2)), (0, (7, 2)), (0, (64, 1)), (0, (256, 2)),
