@@ -281,7 +281,12 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     // carries per velocity: the upwind x-difference D1 of the row the CTU1
     // part reuses, and for CTU2 Y' at row a and dX = X'_{i+1} - X'_i at row
     // a-1 (s_y > 0) or a (s_y < 0)
-    R cD1[16], cY[16], cdX[16];
+    // FP32 CTU1 kernels sum the CTU1 part in FP64 from an FP64 carry (as
+    // fast as their FP32 sum is slow there; CTU2 is the other way round)
+    constexpr bool SUM64 = sizeof(R) == 4 && SCHEME == 1;
+    using CD = std::conditional_t<SUM64, N, R>;
+    CD cD1[16];
+    R cY[16], cdX[16];
     // per-row stencil rings (same indexing by phase): advected density
     // deviation sums and their x-sums (row a), Laplacian rows and their
     // x-differences and x-sums (row a-1), pending 24-neighbour gradient sums
@@ -294,7 +299,10 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         dsr[i] = hsr[i] = Lr[i] = dLr[i] = sLr[i] = ax[i] = ay[i] = N(0);
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) cD1[k] = cY[k] = cdX[k] = R(0);
+    for (int k = 0; k < 16; ++k) {
+        cD1[k] = CD(0);
+        cY[k] = cdX[k] = R(0);
+    }
     if constexpr (ADV) {
         const uint32_t voff = row_voff(y0 - 4);
 #pragma unroll
@@ -362,16 +370,23 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             // repeats step after step).  D1 of the row that is reused one row
             // later is carried in cD1.
             const R ax = C->nu_xi[MX], ay = C->nu_xi[MY];
-            R inc;        // CTU1 part (FOLD: f + CTU1 part)
+            R inc = 0;    // CTU1 part (FOLD: f + CTU1 part)
+            N inc64 = 0;  // SUM64: CTU1 part, plus f without walls
             R corr = 0;   // CTU2 corrections
             if constexpr (SY > 0) {
                 const R rx = fj - from_left(fj);          // R^x at row a
                 const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
                 const R D1 = (SX > 0) ? -rx : rxu;
                 const R D2 = D2m[K];
-                const R Dc = D1, Du = cD1[K];
-                inc = ctu1_part<FOLD>(fj, D2, Dc, Du, ax, ay);
-                cD1[K] = Dc;
+                if constexpr (SUM64) {
+                    const N Dc = (N)D1, Du = cD1[K];
+                    inc64 = __builtin_fma((N)ay, (N)D2, WALLS ? 0.0 : (N)fj) + (N)ax * __builtin_fma((N)ay, Du - Dc, Dc);
+                    cD1[K] = Dc;
+                } else {
+                    const R Dc = D1, Du = cD1[K];
+                    inc = ctu1_part<FOLD>(fj, D2, Dc, Du, ax, ay);
+                    cD1[K] = Dc;
+                }
                 if constexpr (SCHEME == 2) {
                     // X' at row a and its x-difference; dX of row a-1 is carried
                     const R X = mc_half(rx, rxu);
@@ -390,9 +405,15 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R rxu = upwind_x<SX>(rx);
                 const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row a+1
                 const R D2 = fjp - fj;
-                const R Dc = cD1[K], Du = D1p;
-                inc = ctu1_part<FOLD>(fj, D2, Dc, Du, ax, ay);
-                cD1[K] = Du;
+                if constexpr (SUM64) {
+                    const N Dc = cD1[K], Du = (N)D1p;
+                    inc64 = __builtin_fma((N)ay, (N)D2, WALLS ? 0.0 : (N)fj) + (N)ax * __builtin_fma((N)ay, Du - Dc, Dc);
+                    cD1[K] = Du;
+                } else {
+                    const R Dc = cD1[K], Du = D1p;
+                    inc = ctu1_part<FOLD>(fj, D2, Dc, Du, ax, ay);
+                    cD1[K] = Du;
+                }
                 if constexpr (SCHEME == 2) {
                     // X' at row a+1 and its x-difference; dX of row a is carried
                     const R X = mc_half(rx, rxu);
@@ -408,7 +429,10 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             }
             // f + increment in FP64 (FP32 storage: exact from the two FP32
             // operands)
-            if constexpr (FOLD) fs[K] = inc + corr;
+            if constexpr (SUM64) {
+                if constexpr (WALLS) fs[K] = __builtin_fma(keep, inc64, (N)fj);
+                else fs[K] = inc64;
+            } else if constexpr (FOLD) fs[K] = inc + corr;
             else if constexpr (WALLS) fs[K] = __builtin_fma(keep, (N)(inc + corr), (N)fj);
             else fs[K] = (N)fj + (N)(inc + corr);
         });
