@@ -150,7 +150,7 @@ def main():
                     help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the lattice is advanced on a single device; "
+        print("bench.py: the stepper runs on one GPU only (the lattice is advanced on a single device; "
               "--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
