@@ -248,7 +248,8 @@ def main():
         ach64 = BYTES_PER_LUP["f64"] * nodes / (f64["ms_per_step"] * 1e-3) / 1e9
         line["fp64"] = {"mlups": round(f64["mlups"], 1), "ms_per_step": round(f64["ms_per_step"], 5),
                         "achieved_GBs": round(ach64, 1), "frac": round(ach64 / PEAK_HBM_GBS, 4),
-                        "launch": list(f64["launch"])}
+                        "launch": list(f64["launch"]),
+                        "traffic": measured_traffic("step_fp64_ctu%d%s_%d" % (w.scheme, "_reg" if w.regularize else "", w.Lx))}
         line["speedup_fp32dev_over_fp64"] = round(f64["ms_per_step"] / f32["ms_per_step"], 3)
     if err:
         line["error_fp32dev"] = err
