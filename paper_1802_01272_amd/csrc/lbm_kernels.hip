@@ -279,14 +279,21 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     // collision starts from it unrounded.
     R B[4][16];
     // carries per velocity: the upwind x-difference D1 of the row the CTU1
-    // part reuses, and for CTU2 Y' at row a and dX = X'_{i+1} - X'_i at row
-    // a-1 (s_y > 0) or a (s_y < 0)
+    // part reuses, and for CTU2 Y' at row a, dX = X'_{i+1} - X'_i at row
+    // a-1 (s_y > 0) or a (s_y < 0), and the y-difference that the limiter of
+    // row a formed and row a+1 reuses as its D2: R^y at row a+1 (s_y > 0,
+    // D2 = -R^y) or R^y at row a+2 (s_y < 0)
     // FP32 CTU1 kernels sum the CTU1 part in FP64 from an FP64 carry (as
     // fast as their FP32 sum is slow there; CTU2 is the other way round)
     constexpr bool SUM64 = sizeof(R) == 4 && SCHEME == 1;
     using CD = std::conditional_t<SUM64, N, R>;
     CD cD1[16];
-    R cY[16], cdX[16];
+    R cY[16], cdX[16], cR2[16];
+    // The D2 carry saves 16 subtractions per row but changes the compiler's
+    // schedule: at 6144^2 it makes the FP64 CTU2 kernel 2% and the FP32
+    // regularized kernel 4.5% faster, the FP64 regularized kernel 3.5% and
+    // the FP32 CTU2 kernel 0.3% slower, so only the first two use it.
+    constexpr bool CARRY_D2 = SCHEME == 2 && ((sizeof(R) == 8) != REG);
     // per-row stencil rings (same indexing by phase): advected density
     // deviation sums and their x-sums (row a), Laplacian rows and their
     // x-differences and x-sums (row a-1), pending 24-neighbour gradient sums
@@ -301,7 +308,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         cD1[k] = CD(0);
-        cY[k] = cdX[k] = R(0);
+        cY[k] = cdX[k] = cR2[k] = R(0);
     }
     if constexpr (ADV) {
         const uint32_t voff = row_voff(y0 - 4);
@@ -333,7 +340,8 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         const N keep = ghost_a ? 0.0 : 1.0;
         constexpr bool FOLD = sizeof(R) == 8 && !WALLS;
         // Row a-1 is only needed through D2 = f(a-1) - f(a) of the velocities
-        // with s_y > 0: form those, then load row r+1 into its slot B[iM1]
+        // with s_y > 0 (CTU1; CTU2 carries it): form those, then load row r+1
+        // into its slot B[iM1]
         // before any store of this row (loads and stores share one in-order
         // completion counter, so the next row's wait then never waits on
         // this row's stores).
@@ -342,13 +350,21 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             const uint32_t nvoff = row_voff(r + 1);
 #pragma unroll
             for (int k = 0; k < 16; ++k) buf_load(fm1[k], src, k, nvoff, pbytes);
+            // the D2 carry of the first advecting row (the rows it reads are
+            // loaded by the last of these rows)
+            if constexpr (CARRY_D2) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) cR2[k] = (sign_y(k) > 0) ? fp1[k] - f0[k] : cur[k] - fp1[k];
+            }
             if constexpr (ROLE == 1) __syncthreads();
         }
         if constexpr (ADV && WORK) {
+        // CTU1: D2 = f(a-1) - f(a) of the velocities with s_y > 0 (CTU2
+        // carries it from the previous row's limiter)
         R D2m[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-            if (sign_y(k) > 0) D2m[k] = fm1[k] - f0[k];
+            if (!CARRY_D2 && sign_y(k) > 0) D2m[k] = fm1[k] - f0[k];
         {
             const uint32_t nvoff = row_voff(r + 1);
 #pragma unroll
@@ -377,7 +393,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R rx = fj - from_left(fj);          // R^x at row a
                 const R rxu = upwind_x<SX>(rx);           // R^x at i - s_x
                 const R D1 = (SX > 0) ? -rx : rxu;
-                const R D2 = D2m[K];
+                const R D2 = CARRY_D2 ? -cR2[K] : D2m[K];
                 if constexpr (SUM64) {
                     const N Dc = (N)D1, Du = cD1[K];
                     inc64 = __builtin_fma((N)ay, (N)D2, WALLS ? 0.0 : (N)fj) + (N)ax * __builtin_fma((N)ay, Du - Dc, Dc);
@@ -392,7 +408,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     const R X = mc_half(rx, rxu);
                     const R dXj = from_right(X) - X;
                     // Y' at row a+1 (ratio with R^y of row a = -D2); Y' of row a is carried
-                    const R Y1 = mc_half(fp1[K] - fj, -D2);
+                    const R Ry1 = fp1[K] - fj;
+                    const R Y1 = mc_half(Ry1, -D2);
+                    if constexpr (CARRY_D2) cR2[K] = Ry1;
                     const R dY = Y1 - cY[K];
                     corr = C->xs1[MX][MY] * dXj + C->xs2[MX][MY] * cdX[K] + C->ys1[MX][MY] * dY
                          + C->ys2[MX][MY] * upwind_x<SX>(dY);
@@ -404,7 +422,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R rx = fjp - from_left(fjp);        // R^x at row a+1
                 const R rxu = upwind_x<SX>(rx);
                 const R D1p = (SX > 0) ? -rx : rxu;       // D1 of row a+1
-                const R D2 = fjp - fj;
+                const R D2 = CARRY_D2 ? cR2[K] : fjp - fj;
                 if constexpr (SUM64) {
                     const N Dc = cD1[K], Du = (N)D1p;
                     inc64 = __builtin_fma((N)ay, (N)D2, WALLS ? 0.0 : (N)fj) + (N)ax * __builtin_fma((N)ay, Du - Dc, Dc);
@@ -419,7 +437,9 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     const R X = mc_half(rx, rxu);
                     const R dXjp = from_right(X) - X;
                     // Y' at row a+1 (ratio with R^y of row a+2); Y' of row a is carried
-                    const R Y1 = mc_half(D2, cur[K] - fjp);
+                    const R Ry2 = cur[K] - fjp;
+                    const R Y1 = mc_half(D2, Ry2);
+                    if constexpr (CARRY_D2) cR2[K] = Ry2;
                     const R dY = Y1 - cY[K];
                     corr = C->xs1[MX][MY] * cdX[K] + C->xs2[MX][MY] * dXjp + C->ys1[MX][MY] * dY
                          + C->ys2[MX][MY] * upwind_x<SX>(dY);
