@@ -339,6 +339,8 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         // compiler branch around each velocity's advection)
         const N keep = ghost_a ? 0.0 : 1.0;
         constexpr bool FOLD = sizeof(R) == 8 && !WALLS;
+        // FP32 CTU2: the four corrections accumulate onto the CTU1 part
+        constexpr bool ACC = sizeof(R) == 4 && SCHEME == 2;
         // Row a-1 is only needed through D2 = f(a-1) - f(a) of the velocities
         // with s_y > 0 (CTU1; CTU2 carries it): form those, then load row r+1
         // into its slot B[iM1]
@@ -412,8 +414,15 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     const R Y1 = mc_half(Ry1, -D2);
                     if constexpr (CARRY_D2) cR2[K] = Ry1;
                     const R dY = Y1 - cY[K];
-                    corr = C->xs1[MX][MY] * dXj + C->xs2[MX][MY] * cdX[K] + C->ys1[MX][MY] * dY
-                         + C->ys2[MX][MY] * upwind_x<SX>(dY);
+                    if constexpr (ACC) {
+                        inc = __builtin_fmaf(C->xs1[MX][MY], dXj, inc);
+                        inc = __builtin_fmaf(C->xs2[MX][MY], cdX[K], inc);
+                        inc = __builtin_fmaf(C->ys1[MX][MY], dY, inc);
+                        inc = __builtin_fmaf(C->ys2[MX][MY], upwind_x<SX>(dY), inc);
+                    } else {
+                        corr = C->xs1[MX][MY] * dXj + C->xs2[MX][MY] * cdX[K] + C->ys1[MX][MY] * dY
+                             + C->ys2[MX][MY] * upwind_x<SX>(dY);
+                    }
                     cdX[K] = dXj;
                     cY[K] = Y1;
                 }
@@ -441,8 +450,15 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     const R Y1 = mc_half(D2, Ry2);
                     if constexpr (CARRY_D2) cR2[K] = Ry2;
                     const R dY = Y1 - cY[K];
-                    corr = C->xs1[MX][MY] * cdX[K] + C->xs2[MX][MY] * dXjp + C->ys1[MX][MY] * dY
-                         + C->ys2[MX][MY] * upwind_x<SX>(dY);
+                    if constexpr (ACC) {
+                        inc = __builtin_fmaf(C->xs1[MX][MY], cdX[K], inc);
+                        inc = __builtin_fmaf(C->xs2[MX][MY], dXjp, inc);
+                        inc = __builtin_fmaf(C->ys1[MX][MY], dY, inc);
+                        inc = __builtin_fmaf(C->ys2[MX][MY], upwind_x<SX>(dY), inc);
+                    } else {
+                        corr = C->xs1[MX][MY] * cdX[K] + C->xs2[MX][MY] * dXjp + C->ys1[MX][MY] * dY
+                             + C->ys2[MX][MY] * upwind_x<SX>(dY);
+                    }
                     cdX[K] = dXjp;
                     cY[K] = Y1;
                 }
@@ -453,6 +469,10 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 if constexpr (WALLS) fs[K] = __builtin_fma(keep, inc64, (N)fj);
                 else fs[K] = inc64;
             } else if constexpr (FOLD) fs[K] = inc + corr;
+            else if constexpr (ACC) {
+                if constexpr (WALLS) fs[K] = __builtin_fma(keep, (N)inc, (N)fj);
+                else fs[K] = (N)fj + (N)inc;
+            }
             else if constexpr (WALLS) fs[K] = __builtin_fma(keep, (N)(inc + corr), (N)fj);
             else fs[K] = (N)fj + (N)(inc + corr);
         });
