@@ -593,7 +593,7 @@ def test_fp32dev_sheared_ten_thousand_steps_against_fp64():
     shear rate 1e-4, radius 20, T = 0.95) against the FP64 stepper, which
     follows the oracle to 1e-10 over long runs with walls: rho and u (u error
     normalised by the largest |u|) within 1e-5 after 10^4 steps (measured
-    2.9e-6 and 3.5e-6)."""
+    2.8e-6 and 3.5e-6)."""
     w = I.sheared_bubble(1e-4, 192).with_size(192, 192, radius=20.0)
     rho, ux, uy = w.fields()
     r64 = lbm.Run(lbm.Params.from_workload(w, precision=lbm.FP64), rho, ux, uy)
