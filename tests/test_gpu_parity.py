@@ -221,6 +221,26 @@ def test_launch_shape_does_not_change_results(precision, launch):
     assert np.array_equal(got, gpu_step_from(p, f, nsteps=3, launch=launch))
 
 
+@pytest.mark.parametrize("precision,launch", [(0, (8, 2)), (1, (8, 0)), (1, (8, 1))])
+@pytest.mark.parametrize("reg", [0, 1])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_short_chunks_against_oracle(precision, launch, reg, bc):
+    """CTU2 with eight rows per chunk (six chunks, the last one ragged):
+    every chunk starts its row march afresh, so the values carried from row
+    to row (upwind differences, limited slopes, stencil sums) are formed
+    again at each chunk start; the step still equals the oracle's."""
+    p = make_params(130, 45, 2, reg, bc, precision=precision)
+    f = random_state(p, 50 + 2 * reg + bc)
+    if precision:
+        run = lbm.Run(p, 1.0, 0.0, 0.0)
+        run.set_f(f)
+        f = run.get_f()
+        run.close()
+    got = gpu_step_from(p, f, launch=launch)
+    ref = o.step(oracle_params(p), f)
+    assert rel_err(got, ref) < (F64_STEP if precision == 0 else F32_STEP)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_rejects_four_waves_per_group(precision):
     """The step kernels hold 32 KiB of LDS per wavefront: four per workgroup
