@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+VALU_SIMDS, CLOCK_HZ = 256 * 4, 2.4e9   # MI355X: 256 CUs x 4 SIMDs, peak engine clock
 BYTES_PER_LUP = {"f32": 128.0, "f64": 256.0}  # read + write 16 distributions once
 
 
@@ -31,6 +32,23 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_1802_01272_amd", "csrc", n), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def measured_valu(kernel_key, launch):
+    """VALU instructions per launch (rocprofv3 SQ_INSTS_VALU) from the
+    committed counter summary, if it was taken on the current kernel source
+    and in this launch shape (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(kernel_key)
+    if (not entry or entry.get("source_hash") != kernel_source_hash()
+            or list(entry.get("launch", [])) != list(launch)):
+        return None
+    return entry.get("valu_per_launch")
 
 
 def measured_traffic(kernel_key):
@@ -243,6 +261,13 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic("step_fp32dev_ctu%d%s_%d" % (w.scheme, "_reg" if w.regularize else "", w.Lx))},
     }
+    # the second bound of the same kernel: VALU issue (one wavefront
+    # instruction per SIMD every 4 cycles, 1024 SIMDs at 2.4 GHz)
+    valu = measured_valu("step_fp32dev_ctu%d%s_%d" % (w.scheme, "_reg" if w.regularize else "", w.Lx), f32["launch"])
+    if valu:
+        ceiling_ms = valu * 4 / (VALU_SIMDS * CLOCK_HZ) * 1e3
+        line["valu_bound"] = {"instructions_per_launch": valu, "ceiling_ms": round(ceiling_ms, 4),
+                              "frac": round(ceiling_ms / f32["ms_per_step"], 4)}
     if "f64" in results:
         f64 = results["f64"]
         ach64 = BYTES_PER_LUP["f64"] * nodes / (f64["ms_per_step"] * 1e-3) / 1e9
