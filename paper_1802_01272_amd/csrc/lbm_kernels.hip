@@ -210,10 +210,13 @@ __device__ __forceinline__ R mc_half(R r, R ru)
     return minmod(minmod(r, ru), R(0.25) * (r + ru));
 }
 
-// weights of the 24-neighbour isotropic gradient, by |e|^2
+// weights of the fourth-order isotropic 5x5 gradient, by |e|^2: exact to
+// fourth order, isotropic fifth-order error, no cos(4 theta) term at seventh
+// order; along an axis it is the central difference (2/3, -1/12).  The
+// |e|^2 = 4 shell has weight 0.
 template <typename R> struct G5W {
-    static constexpr R w1 = R(4.0 / 21.0), w2 = R(4.0 / 45.0), w4 = R(1.0 / 60.0),
-                       w5 = R(2.0 / 315.0), w8 = R(1.0 / 5040.0);
+    static constexpr R w1 = R(2.0 / 5.0), w2 = R(7.0 / 45.0), w4 = R(0.0),
+                       w5 = R(-1.0 / 45.0), w8 = R(1.0 / 720.0);
 };
 
 // ----------------------------------------------------------------------------
@@ -296,7 +299,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     constexpr bool CARRY_D2 = SCHEME == 2 && ((sizeof(R) == 8) != REG);
     // per-row stencil rings (same indexing by phase): advected density
     // deviation sums and their x-sums (row a), Laplacian rows and their
-    // x-differences and x-sums (row a-1), pending 24-neighbour gradient sums
+    // x-differences and x-sums (row a-1), pending 5x5 gradient sums
     // (rows a-2 .. a+1)
     N dsr[4], hsr[4], Lr[4], dLr[4], sLr[4], ax[4], ay[4];
 #pragma unroll
@@ -568,7 +571,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         dLr[iN] = dL_m1;
         sLr[iN] = sL_m1;
 
-        // 24-neighbour isotropic gradient of p^i - p^w: row a adds to rows
+        // fourth-order 5x5 gradient of p^i - p^w: row a adds to rows
         // a-2 .. a+2; ax/ay[(P + d) mod 4] hold the sums of row a-2+d
         N g5x, g5y;
         {
@@ -576,11 +579,12 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             const N p1 = from_right(phi_r), m1 = from_left(phi_r);
             const N p2 = from_right(p1), m2 = from_left(m1);
             const N dx1 = p1 - m1, dx2 = p2 - m2, s1 = p1 + m1, s2 = p2 + m2;
-            const N A0 = W::w1 * dx1 + 2.0 * W::w4 * dx2;
+            static_assert(W::w4 == 0.0, "the |e|^2 = 4 shell is dropped below");
+            const N A0 = W::w1 * dx1;
             const N A1 = W::w2 * dx1 + 2.0 * W::w5 * dx2;
             const N A2 = W::w5 * dx1 + 2.0 * W::w8 * dx2;
             const N B1 = W::w1 * phi_r + W::w2 * s1 + W::w5 * s2;
-            const N B2 = W::w4 * phi_r + W::w5 * s1 + W::w8 * s2;
+            const N B2 = W::w5 * s1 + W::w8 * s2;
             g5x = ax[iN] + A2;
             g5y = ay[iN] + 2.0 * B2;
             ax[iM1] += A1;
