@@ -144,6 +144,61 @@ def batched_sweep(args, torch, I, lbm, graph_steps=20):
             "speedup_batched_over_sequential": round(ms_seq / ms_batch, 3)}
 
 
+def copy_probe(args, torch):
+    """Memory-side ceilings of the step's access shape on the 16-plane FP32
+    field of args.L^2 nodes: plain copies (no arithmetic) that move the step's
+    algorithmic bytes (read and write every distribution once) in the step's
+    strip-marching pattern and in simpler ones; GB/s of algorithmic bytes,
+    HIP events, best and median of `reps` launches each."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1802_01272_amd", "_lib", "libprobe.so"))
+    lib.probe_strip_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 6 + [ctypes.c_void_p]
+    lib.probe_flat_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    L, reps = args.L, 20
+    n = 16 * L * L
+    src = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    algo = 2.0 * 4 * n
+    variants = []
+    # (name, outw, rows, halo_y, lds bytes per workgroup); 36 KiB of LDS holds
+    # a CU to 4 wavefronts, the number of loading wavefronts of the step's
+    # pair launch
+    for outw, hy, rows, lds in ((56, 4, 32, 0), (56, 4, 32, 36864), (56, 0, 32, 0), (64, 4, 32, 0),
+                                (64, 4, 32, 36864), (64, 0, 32, 0), (56, 4, 128, 0), (64, 4, 128, 0)):
+        variants.append(("strip%d_rows%d_halo%d%s" % (outw, rows, hy, "_4waves_per_cu" if lds else ""),
+                         lambda outw=outw, rows=rows, hy=hy, lds=lds: lib.probe_strip_copy(
+                             src.data_ptr(), dst.data_ptr(), L, L, outw, rows, hy, lds, sp)))
+    variants.append(("flat_float4", lambda: lib.probe_flat_copy(src.data_ptr(), dst.data_ptr(), n, sp)))
+    out = {}
+    for name, fn in variants:
+        rc = fn()
+        if rc != 0:
+            raise RuntimeError("probe %s failed: hip error %d" % (name, rc))
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        times.sort()
+        out[name] = {"best_ms": round(times[0], 4), "median_ms": round(times[len(times) // 2], 4),
+                     "GBs_best": round(algo / (times[0] * 1e-3) / 1e9, 1),
+                     "GBs_median": round(algo / (times[len(times) // 2] * 1e-3) / 1e9, 1)}
+        print("[copy-probe] %-34s best %.4f ms (%.0f GB/s), median %.4f ms (%.0f GB/s)"
+              % (name, times[0], out[name]["GBs_best"], times[len(times) // 2], out[name]["GBs_median"]),
+              file=sys.stderr, flush=True)
+    ok = bool(torch.equal(src.view(16, L, L)[:, :, :64], dst.view(16, L, L)[:, :, :64]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"metric": "copy ceilings of the step's access shape", "unit": "GB/s (algorithmic bytes)",
+            "bytes_per_launch": algo, "lattice": [L, L], "planes": 16, "dtype": "f32", "reps": reps,
+            "last_copy_matches_source": ok, "variants": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +219,9 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="instead of the 6144^2 lattice: the 32-run sweep of uneven lattices in one batched, "
                          "graph-captured launch per step against the same runs stepped one after another")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="instead of the stepper: plain copies of the FP32 field in the step's access shape and "
+                         "simpler ones (memory-side ceilings, GB/s of algorithmic bytes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -180,6 +238,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batched:
         print(json.dumps(batched_sweep(args, torch, I, lbm)), flush=True)
+        return
+    if args.copy_probe:
+        print(json.dumps(copy_probe(args, torch)), flush=True)
         return
     if args.copy_calibration:
         src_t = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)

@@ -1,5 +1,7 @@
-"""Build step of the HIP library: compiles csrc/*.hip for gfx950 into
-_lib/liblbm.so (in-tree, so it travels with the source tree)."""
+"""Build step of the HIP libraries: compiles the stepper (csrc/lbm_kernels.hip,
+csrc/lbm_api.hip) for gfx950 into _lib/liblbm.so, and the copy probe used by
+bench.py's memory-side measurement (csrc/copy_probe.hip) into
+_lib/libprobe.so (in-tree, so they travel with the source tree)."""
 from __future__ import annotations
 
 import os
@@ -10,6 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = [os.path.join(HERE, "csrc", n) for n in ("lbm_kernels.hip", "lbm_api.hip")]
 LIB = os.path.join(HERE, "_lib", "liblbm.so")
+PROBE_SRC = [os.path.join(HERE, "csrc", "copy_probe.hip")]
+PROBE_LIB = os.path.join(HERE, "_lib", "libprobe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -22,9 +26,9 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    cmd = [HIPCC] + FLAGS + ["-shared"] + SRC + ["-o", LIB + ".tmp"]
+def _hipcc(sources, lib, verbose):
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    cmd = [HIPCC] + FLAGS + ["-shared"] + sources + ["-o", lib + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -34,8 +38,13 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + err)
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(PROBE_SRC, PROBE_LIB, verbose)
+    return _hipcc(SRC, LIB, verbose)
 
 
 if __name__ == "__main__":
