@@ -197,6 +197,32 @@ lbm_status lbm_set_f_device(lbm_run* run, const double* d_f, void* stream);
  * Returns LBM_ENONFINITE (with *out filled) when n_nonfinite > 0.  sync. */
 lbm_status lbm_reduce(lbm_run* run, double rho_threshold, lbm_stats* out, void* stream);
 
+/* The current distribution field of a run, in the library's storage layout:
+ * 16 planes of *plane_stride values each, plane k at d_f + k * plane_stride
+ * values; within a plane node (i, j) at j * Lx + i, followed with shear walls
+ * by the two ghost rows (row Ly: below the lattice, row Ly + 1: above).  FP64
+ * values f_k for LBM_FP64 storage, FP32 deviations f_k - w_k rho_ref for
+ * LBM_FP32_DEV.  The pointer lies inside the run's workspace and changes with
+ * every step (two fields alternate). */
+lbm_status lbm_state_device(const lbm_run* run, const void** d_f, int64_t* plane_stride);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): the diagnostics of
+ * lbm_reduce for a distribution field d_f the caller holds in the storage
+ * layout of lbm_state_device for parameters p (validated as lbm_validate
+ * does), without a run handle or a workspace.  It allocates nothing: the
+ * partial sums, results and coefficient block live in a fixed device array of
+ * the library (about 168 KiB per GPU, 2048 workgroups' partials whatever the
+ * lattice size, kept until the process ends); every lattice lbm_validate
+ * accepts fits (at most 2^26 nodes per plane), larger ones are rejected with
+ * LBM_EINVAL.  All calls on one GPU share that array: calls that overlap in
+ * time on one GPU (from several host threads or streams) race and must be
+ * serialised by the caller.  Nothing in it needs clearing between calls.
+ * Same results, bit for bit, as lbm_reduce on a run holding the same field.
+ * sync. */
+lbm_status lbm_reduce_field_static(const lbm_params* p, const void* d_f, double rho_threshold, lbm_stats* out,
+                                  void* stream);
+
 /* Launch shape: rows of the lattice each strip of 56 columns advances per
  * workgroup (>= 1), and waves_per_group: 1 or 2 wavefronts per workgroup,
  * each marching its own strip (the step kernels keep 32 KiB of LDS per

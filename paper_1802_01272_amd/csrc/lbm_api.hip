@@ -439,7 +439,7 @@ lbm_status set_plane(lbm_run* r, int k, const double* d_in, hipStream_t s)
     return LBM_OK;
 }
 
-void derive_stats(const lbm_run* r, const double* v, lbm_stats* o)
+void derive_stats(const lbm_params& p, const double* v, lbm_stats* o)
 {
     std::memset(o, 0, sizeof(*o));
     o->mass = v[0];
@@ -453,11 +453,11 @@ void derive_stats(const lbm_run* r, const double* v, lbm_stats* o)
     o->sxy = v[8];
     o->syy = v[9];
     const double N = (double)o->n_bubble;
-    o->A_rel = N / ((double)r->p.Lx * (double)r->p.Ly);
-    o->R_eq = r->p.ds * std::sqrt(N / M_PI);
+    o->A_rel = N / ((double)p.Lx * (double)p.Ly);
+    o->R_eq = p.ds * std::sqrt(N / M_PI);
     if (o->n_bubble > 0) {
-        o->cx = o->sx / N + 0.5 * (r->p.Lx - 1);
-        o->cy = o->sy / N + 0.5 * (r->p.Ly - 1);
+        o->cx = o->sx / N + 0.5 * (p.Lx - 1);
+        o->cy = o->sy / N + 0.5 * (p.Ly - 1);
         const double mx = o->sx / N, my = o->sy / N;
         o->Txx = o->sxx / N - mx * mx;
         o->Txy = o->sxy / N - mx * my;
@@ -472,6 +472,71 @@ void derive_stats(const lbm_run* r, const double* v, lbm_stats* o)
     }
 }
 
+}  // namespace
+
+// ============================================================================
+// Device scratch of the allocation-free entry point (lbm_reduce_field_static):
+// a file-scope array, one copy per GPU, resolved per device with
+// hipGetSymbolAddress.  In host code `scratch` names a host-side stand-in,
+// never the device memory: only the resolved pointer is passed on.
+
+namespace {
+// coefficient block (either precision), then the block partials and the
+// REDUCE_VALUES results of the reduction
+constexpr size_t SCRATCH_COEF_BYTES = 8192;
+static_assert(sizeof(StepCoef<double>) <= SCRATCH_COEF_BYTES && sizeof(StepCoef<float>) <= SCRATCH_COEF_BYTES,
+              "scratch coefficient slot");
+constexpr size_t SCRATCH_BYTES = SCRATCH_COEF_BYTES + RED_BYTES;
+}  // namespace
+
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// device address of the current device's copy of `scratch` (looked up on
+// the first call on that device)
+lbm_status scratch_of_current_device(char** out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "scratch: current device");
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(LBM_EDEVICE, "scratch: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch: hipGetSymbolAddress");
+        if (!ptr) return fail(LBM_EDEVICE, "scratch: null symbol address");
+        g_scratch_dev[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return LBM_OK;
+}
+
+template <typename R>
+lbm_status reduce_field_static(const lbm_params* p, const void* d_f, double threshold, lbm_stats* out,
+                               hipStream_t s)
+{
+    char* scr = nullptr;
+    lbm_status st = scratch_of_current_device(&scr);
+    if (st != LBM_OK) return st;
+    StepCoef<R> c;
+    fill_coef<R>(p, c);
+    StepCoef<R>* d_coef = reinterpret_cast<StepCoef<R>*>(scr);
+    double* partials = reinterpret_cast<double*>(scr + SCRATCH_COEF_BYTES);
+    double* result = partials + (size_t)REDUCE_MAX_BLOCKS * REDUCE_VALUES;
+    HIP_TRY(hipMemcpyAsync(d_coef, &c, sizeof(c), hipMemcpyHostToDevice, s), "reduce_field_static: coefficients");
+    HIP_TRY(launch_reduce<R>(static_cast<const R*>(d_f), d_coef, p->Lx, p->Ly, plane_of(p), threshold, partials,
+                             REDUCE_MAX_BLOCKS, result, s),
+            "reduce_field_static: launch");
+    double v[REDUCE_VALUES];
+    HIP_TRY(hipMemcpyAsync(v, result, sizeof(v), hipMemcpyDeviceToHost, s), "reduce_field_static: download");
+    HIP_TRY(hipStreamSynchronize(s), "reduce_field_static");
+    derive_stats(*p, v, out);
+    if (out->n_nonfinite > 0) return fail(LBM_ENONFINITE, "non-finite distribution values in the state");
+    return LBM_OK;
+}
 }  // namespace
 
 // ============================================================================
@@ -657,9 +722,21 @@ lbm_status lbm_reduce(lbm_run* run, double rho_threshold, lbm_stats* out, void* 
     double v[REDUCE_VALUES];
     HIP_TRY(hipMemcpyAsync(v, result, sizeof(v), hipMemcpyDeviceToHost, s), "reduce download");
     HIP_TRY(hipStreamSynchronize(s), "reduce");
-    derive_stats(run, v, out);
+    derive_stats(run->p, v, out);
     if (out->n_nonfinite > 0) return fail(LBM_ENONFINITE, "non-finite distribution values in the state");
     return LBM_OK;
+}
+
+lbm_status lbm_reduce_field_static(const lbm_params* p, const void* d_f, double rho_threshold, lbm_stats* out,
+                                  void* stream)
+{
+    if (!p || !d_f || !out) return fail(LBM_EINVAL, "null argument");
+    lbm_status st = validate(p);
+    if (st != LBM_OK) return st;
+    if (!is_finite_d(rho_threshold)) return fail(LBM_EINVAL, "threshold must be finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return p->precision == LBM_FP32_DEV ? reduce_field_static<float>(p, d_f, rho_threshold, out, s)
+                                        : reduce_field_static<double>(p, d_f, rho_threshold, out, s);
 }
 
 lbm_status lbm_set_launch(lbm_run* run, int32_t rows_per_wave, int32_t waves_per_group)
@@ -752,6 +829,14 @@ lbm_status lbm_autotune(const lbm_params* p, void* d_ws, size_t ws_bytes, void* 
 void lbm_destroy(lbm_run* run)
 {
     if (run && !run->batch) delete run;
+}
+
+lbm_status lbm_state_device(const lbm_run* run, const void** d_f, int64_t* plane_stride)
+{
+    if (!run || !d_f || !plane_stride) return fail(LBM_EINVAL, "null argument");
+    *d_f = run->field[run->cur];
+    *plane_stride = plane_of(&run->p);
+    return LBM_OK;
 }
 
 // ---------------------------------------------------------------------------

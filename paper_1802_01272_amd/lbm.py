@@ -122,6 +122,8 @@ def _load():
         "lbm_get_f_device": ([vp, vp, vp], st),
         "lbm_set_f_device": ([vp, vp, vp], st),
         "lbm_reduce": ([vp, ctypes.c_double, ctypes.POINTER(CStats), vp], st),
+        "lbm_state_device": ([vp, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64)], st),
+        "lbm_reduce_field_static": ([P, vp, ctypes.c_double, ctypes.POINTER(CStats), vp], st),
         "lbm_set_launch": ([vp, ctypes.c_int32, ctypes.c_int32], st),
         "lbm_get_launch": ([vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], st),
         "lbm_autotune": ([P, vp, ctypes.c_size_t, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -285,6 +287,13 @@ class Run:
         _check(st)
         return _stats_dict(cs)
 
+    def state_device(self):
+        """(device address, plane stride in values) of the current distribution
+        field in the library's storage layout (see lbm_state_device)."""
+        ptr, stride = ctypes.c_void_p(), ctypes.c_int64()
+        _check(LIB.lbm_state_device(self.handle, ctypes.byref(ptr), ctypes.byref(stride)))
+        return ptr.value, stride.value
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             LIB.lbm_destroy(self.handle)
@@ -295,6 +304,22 @@ class Run:
             self.close()
         except Exception:
             pass
+
+
+def reduce_field_static(p: Params, d_f: int, threshold: float, stream=None,
+                        allow_nonfinite: bool = False) -> Dict[str, float]:
+    """lbm_reduce_field_static: diagnostics of a device field at address d_f
+    (storage layout of Run.state_device) without a run or a workspace; the
+    library's own fixed device scratch holds the partial sums."""
+    torch = _torch()
+    cp = p.c()
+    cs = CStats()
+    st = LIB.lbm_reduce_field_static(ctypes.byref(cp), ctypes.c_void_p(d_f), float(threshold), ctypes.byref(cs),
+                                     _stream_handle(torch, stream))
+    if st == LBM_ENONFINITE and allow_nonfinite:
+        return _stats_dict(cs)
+    _check(st)
+    return _stats_dict(cs)
 
 
 def autotune(p: Params, steps_per_trial: int = 5, stream=None):
