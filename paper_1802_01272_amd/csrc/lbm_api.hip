@@ -110,6 +110,7 @@ void fill_coef(const lbm_params* p, StepCoef<R>& c)
     for (int mx = 0; mx < 2; ++mx) {
         const double ax = nu * q[mx], k2x = q[mx] * (1 - ax);
         c.nu_xi[mx] = (R)ax;
+        c.nu_xi_d[mx] = ax;
         for (int my = 0; my < 2; ++my) {
             const double ay = nu * q[my], k2y = q[my] * (1 - ay);
             c.xs1[mx][my] = (R)(-nu * (1 - ay) * k2x);

@@ -63,6 +63,8 @@ struct StepCoef {
     R ys2[2][2];   // -nu  nu |xi_x|      k2[my]   weight of dY at the column upwind in x
     R ghost_lo[16], ghost_hi[16];          // stored values of the two wall ghost-row states
     // node-local terms, always FP64
+    double nu_xi_d[2];  // nu |xi| in FP64: the CTU1 weights of the FP64 sum that
+                        // FP32 storage uses
     double rho0;        // rho_ref (deviation storage) or 0
     double T, Tm1;      // T and T - 1
     double a_vdw, b_vdw;

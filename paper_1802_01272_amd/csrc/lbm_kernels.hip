@@ -40,11 +40,11 @@
 //    arithmetic (moments, stencils, collision and force) is FP64 in both
 //    storage modes.  With FP32 storage, a rounding that repeats identically
 //    from step to step where the flow is nearly steady adds up coherently, so
-//    the FP32 path avoids such roundings: the CTU1 weights are only nu |xi_x|
-//    and nu |xi_y| (a weight set that stays consistent when rounded), the
-//    advected value f + (A f - f) is formed in FP64 (exact from the FP32
-//    operands), and the new deviation is rounded to FP32 stochastically
-//    (unbiased, seeded per step).
+//    the FP32 path avoids such roundings: the CTU1 part of the increment is
+//    summed in FP64 with FP64 weights nu |xi_x| and nu |xi_y| (only the CTU2
+//    corrections are FP32), the advected value f + (A f - f) is formed in
+//    FP64, and the new deviation is rounded to FP32 stochastically (unbiased,
+//    seeded per step).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -286,9 +286,12 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     // a-1 (s_y > 0) or a (s_y < 0), and the y-difference that the limiter of
     // row a formed and row a+1 reuses as its D2: R^y at row a+1 (s_y > 0,
     // D2 = -R^y) or R^y at row a+2 (s_y < 0)
-    // FP32 CTU1 kernels sum the CTU1 part in FP64 from an FP64 carry (as
-    // fast as their FP32 sum is slow there; CTU2 is the other way round)
-    constexpr bool SUM64 = sizeof(R) == 4 && SCHEME == 1;
+    // FP32 storage sums the CTU1 part in FP64, with FP64 weights nu |xi| and
+    // an FP64 carry of D1: FP32-rounded weights shift the effective advection
+    // speed by a few 1e-8 every step, which moves a growing bubble's interface
+    // coherently (after 10^4 steps on a 1024^2 cavitation run, rho and u
+    // errors at the interface 3-4x larger).  The CTU2 corrections stay FP32.
+    constexpr bool SUM64 = sizeof(R) == 4;
     using CD = std::conditional_t<SUM64, N, R>;
     CD cD1[16];
     R cY[16], cdX[16], cR2[16];
@@ -391,6 +394,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             // repeats step after step).  D1 of the row that is reused one row
             // later is carried in cD1.
             const R ax = C->nu_xi[MX], ay = C->nu_xi[MY];
+            const N axd = C->nu_xi_d[MX], ayd = C->nu_xi_d[MY];
             R inc = 0;    // CTU1 part (FOLD: f + CTU1 part)
             N inc64 = 0;  // SUM64: CTU1 part, plus f without walls
             R corr = 0;   // CTU2 corrections
@@ -401,7 +405,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R D2 = CARRY_D2 ? -cR2[K] : D2m[K];
                 if constexpr (SUM64) {
                     const N Dc = (N)D1, Du = cD1[K];
-                    inc64 = __builtin_fma((N)ay, (N)D2, WALLS ? 0.0 : (N)fj) + (N)ax * __builtin_fma((N)ay, Du - Dc, Dc);
+                    inc64 = __builtin_fma(ayd, (N)D2, WALLS ? 0.0 : (N)fj) + axd * __builtin_fma(ayd, Du - Dc, Dc);
                     cD1[K] = Dc;
                 } else {
                     const R Dc = D1, Du = cD1[K];
@@ -437,7 +441,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                 const R D2 = CARRY_D2 ? cR2[K] : fjp - fj;
                 if constexpr (SUM64) {
                     const N Dc = cD1[K], Du = (N)D1p;
-                    inc64 = __builtin_fma((N)ay, (N)D2, WALLS ? 0.0 : (N)fj) + (N)ax * __builtin_fma((N)ay, Du - Dc, Dc);
+                    inc64 = __builtin_fma(ayd, (N)D2, WALLS ? 0.0 : (N)fj) + axd * __builtin_fma(ayd, Du - Dc, Dc);
                     cD1[K] = Du;
                 } else {
                     const R Dc = cD1[K], Du = D1p;
@@ -469,8 +473,11 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             // f + increment in FP64 (FP32 storage: exact from the two FP32
             // operands)
             if constexpr (SUM64) {
-                if constexpr (WALLS) fs[K] = __builtin_fma(keep, inc64, (N)fj);
-                else fs[K] = inc64;
+                // CTU2: plus the FP32 corrections accumulated in inc
+                N sum = inc64;
+                if constexpr (SCHEME == 2) sum += (N)inc;
+                if constexpr (WALLS) fs[K] = __builtin_fma(keep, sum, (N)fj);
+                else fs[K] = sum;
             } else if constexpr (FOLD) fs[K] = inc + corr;
             else if constexpr (ACC) {
                 if constexpr (WALLS) fs[K] = __builtin_fma(keep, (N)inc, (N)fj);

