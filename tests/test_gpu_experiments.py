@@ -1,0 +1,158 @@
+"""The paper's Sec. II D and III A experiments on the HIP stepper.
+
+* Critical radius (Sec. III A, Eq. raggio_c): vapour bubbles (rho_V = 0.2396)
+  in superheated liquid held at rho_ext beyond R_BC = L/2 - 1/(2 ds) nodes
+  (the far-field clamp), T = 0.8, kappa = 1e-4, tau = 1e-3, dt = 1e-4,
+  ds = 1/256, CTU2, FP64, L = 1024.  A bubble has shrunk (grown) once its
+  equivalent radius is 3 nodes below (above) its initial radius.  The paper
+  finds the simulated R_c slightly above Eq. raggio_c (76.5 against 75.5 ds
+  at rho_ext = 1.923).  Here the bisection gives 79.5 ds at 1.923 (and 60.5,
+  43.5, 34.5 ds at 1.920, 1.915, 1.910): 4-5% above Eq. raggio_c.  The flat
+  interface under the same numerics relaxes to a liquid density 0.03% below
+  the Maxwell value, which trims the superheat rho_L - rho_ext by 6% at
+  rho_ext = 1.923; scaling Eq. raggio_c by that superheat ratio gives 79-80 ds.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import thermo
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_1802_01272_amd.lbm")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(HERE, "golden", "paper_values.json")) as fh:
+    PAPER = json.load(fh)
+
+T, DS, DT, TAU, KAPPA, L = 0.8, 1.0 / 256, 1e-4, 1e-3, 1e-4, 1024
+
+
+def bubble_fate(rho_ext, R0, max_steps=400000, every=5000):
+    """+1 if a bubble of initial radius R0 nodes grows by 3 nodes, -1 if it
+    shrinks by 3, 0 if neither within max_steps."""
+    from paper_1802_01272_amd import inputs as I
+    rv, rl = thermo.maxwell(T)
+    rho = I.bubble(L, L, PAPER["coexistence_T0.8"]["rho_V"], rho_ext, R0, 4.0)
+    p = lbm.Params(Lx=L, Ly=L, ds=DS, dt=DT, tau=TAU, T=T, kappa=KAPPA, scheme=2, precision=lbm.FP64,
+                   clamp_radius=L / 2 - 0.5 / DS, clamp_rho=rho_ext)
+    run = lbm.Run(p, rho, 0.0, 0.0)
+    fate, s, r = 0, 0, R0
+    while s < max_steps:
+        run.step(every)
+        s += every
+        r = run.reduce(0.5 * (rv + rl))["R_eq"] / DS
+        if abs(r - R0) > 3:
+            fate = 1 if r > R0 else -1
+            break
+    run.close()
+    print("rho_ext %.4f R0 %d: %s after %d steps (R_eq %.2f)" % (rho_ext, R0, {1: "grows", -1: "shrinks", 0: "?"}[fate], s, r),
+          flush=True)
+    return fate
+
+
+def relaxed_coexistence_T08():
+    rho = np.loadtxt(os.path.join(HERE, "golden", "flat_interface_T0.8.txt"))
+    return float(rho[0]), float(rho[len(rho) // 2])
+
+
+def test_critical_radius_by_bisection():
+    g = PAPER["critical_radius"]
+    sigma = PAPER["surface_tension_T0.8_kappa1e-4"]["ds_1_256"]
+    rho_ext = g["rho_ext"]
+    pred = thermo.critical_radius(T, rho_ext, sigma) / DS
+    lo, hi = int(math.floor(pred)), int(math.ceil(1.1 * pred))
+    assert bubble_fate(rho_ext, lo) == -1 and bubble_fate(rho_ext, hi) == 1
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        f = bubble_fate(rho_ext, mid)
+        assert f != 0
+        lo, hi = (mid, hi) if f < 0 else (lo, mid)
+    rc = 0.5 * (lo + hi)
+    _, rl_relaxed = relaxed_coexistence_T08()
+    rl = thermo.maxwell(T)[1]
+    superheat_scaled = pred * (rl - rho_ext) / (rl_relaxed - rho_ext)
+    print("R_c = %.1f ds; Eq. raggio_c %.2f ds (paper's simulations %.1f); scaled to the relaxed liquid density %.2f ds"
+          % (rc, pred, g["R_c_over_ds"], superheat_scaled))
+    # above the prediction, as in the paper (the scaled value moves by about
+    # 6% per 0.03% of the liquid density, so it is reported, not pinned)
+    assert pred < rc < 1.08 * pred
+
+
+def test_critical_radius_bracket_at_lower_superheat():
+    sigma = PAPER["surface_tension_T0.8_kappa1e-4"]["ds_1_256"]
+    rho_ext = 1.915
+    pred = thermo.critical_radius(T, rho_ext, sigma) / DS
+    assert bubble_fate(rho_ext, int(math.floor(pred))) == -1
+    assert bubble_fate(rho_ext, int(math.ceil(1.06 * pred))) == 1
+
+
+# --------------------------------------------------------------------------
+# Regularization and isotropy of decaying shear waves (Sec. II D, Eq. ereg,
+# Figs. newfigureg and newfiguregg): ideal gas, rho = T = 1, wavelength 2,
+# U = 0.01, dt = 1e-4.  The apparent viscosity nu = ln(U / u_perp(0, t)) /
+# (k^2 t) at t = 2 / (tau pi^2) (amplitude near e^-2) is read for waves along
+# an axis (L ds = 2) and along the diagonal (L ds = 2 sqrt 2), on the lattice
+# spacing ds and on ds / sqrt 2, with and without regularization.
+
+def shear_wave_nu(tau, ds, scheme, diagonal, reg, t_end, dt=1e-4, U=0.01):
+    L = int(round((2.0 * math.sqrt(2.0) if diagonal else 2.0) / ds))
+    x = np.arange(L) * ds
+    X, Y = np.meshgrid(x, x)
+    k = 2 * math.pi / (L * ds)
+    kx, ky = (k, k) if diagonal else (k, 0.0)
+    e = (-1 / math.sqrt(2), 1 / math.sqrt(2)) if diagonal else (0.0, 1.0)
+    ph = np.cos(kx * X + ky * Y)
+    p = lbm.Params(Lx=L, Ly=L, ds=ds, dt=dt, tau=tau, T=1.0, a=0.0, b=0.0, kappa=0.0, scheme=scheme,
+                   regularize=reg, precision=lbm.FP64, rho_ref=1.0)
+    run = lbm.Run(p, np.ones((L, L)), U * ph * e[0], U * ph * e[1])
+    run.step(int(round(t_end / dt)))
+    _, vx, vy = run.moments()
+    run.close()
+    u = vx[0, 0] * e[0] + vy[0, 0] * e[1]
+    return math.log(U / u) / ((kx * kx + ky * ky) * t_end)
+
+
+def test_regularization_restores_isotropy_ctu2():
+    """CTU2 on ds = 1/256 (Fig. newfiguregg): at tau = 0.01 regularization
+    changes nothing by t = 2 (within 1e-3; 6e-4 apart during the first half
+    time unit); for tau > 0.1 the unregularized axial and diagonal waves
+    decay differently (measured 16% and 12% apart at tau = 0.2, 0.3) while the
+    diagonal waves agree across ds; regularized, all agree (to 2e-4)."""
+    ds = 1.0 / 256
+    a0, a1 = (shear_wave_nu(0.01, ds, 2, False, r, 2.0) for r in (0, 1))
+    print("tau 0.01 axial: nu %.6e plain, %.6e regularized" % (a0, a1))
+    assert a1 == pytest.approx(a0, rel=1e-3)
+    for tau in (0.2, 0.3):
+        t = 2.0 / (tau * math.pi ** 2)
+        ax0, dg0 = shear_wave_nu(tau, ds, 2, False, 0, t), shear_wave_nu(tau, ds, 2, True, 0, t)
+        ax1, dg1 = shear_wave_nu(tau, ds, 2, False, 1, t), shear_wave_nu(tau, ds, 2, True, 1, t)
+        print("tau %.1f: plain axial %.5f diagonal %.5f; regularized axial %.5f diagonal %.5f"
+              % (tau, ax0, dg0, ax1, dg1))
+        assert abs(ax0 - dg0) / dg0 > 0.05
+        assert abs(ax1 - dg1) / dg1 < 1e-3
+    t = 2.0 / (0.2 * math.pi ** 2)
+    dg_fine = shear_wave_nu(0.2, ds / math.sqrt(2.0), 2, True, 0, t)
+    dg = shear_wave_nu(0.2, ds, 2, True, 0, t)
+    print("tau 0.2 plain diagonal: ds %.6f nu %.5f, ds / sqrt 2 nu %.5f" % (ds, dg, dg_fine))
+    assert dg_fine == pytest.approx(dg, rel=1e-3)
+
+
+def test_regularization_restores_isotropy_ctu1():
+    """CTU1 on ds = 1/128 (Fig. newfigureg): unregularized axial and diagonal
+    waves differ at tau = 0.2 (14%); regularized, the axial wave agrees with the
+    diagonal one on ds / sqrt 2, whose numerical viscosity matches the axial
+    one's (within 1%)."""
+    ds, tau = 1.0 / 128, 0.2
+    t = 2.0 / (tau * math.pi ** 2)
+    ax0, dg0 = shear_wave_nu(tau, ds, 1, False, 0, t), shear_wave_nu(tau, ds, 1, True, 0, t)
+    ax1 = shear_wave_nu(tau, ds, 1, False, 1, t)
+    dg1_fine = shear_wave_nu(tau, ds / math.sqrt(2.0), 1, True, 1, t)
+    print("CTU1 tau 0.2: plain axial %.5f diagonal %.5f; regularized axial %.5f, diagonal on ds/sqrt2 %.5f"
+          % (ax0, dg0, ax1, dg1_fine))
+    assert abs(ax0 - dg0) / dg0 > 0.05
+    assert abs(ax1 - dg1_fine) / dg1_fine < 0.01

@@ -1,0 +1,81 @@
+"""The benchmark's synthetic workloads against the FP64 references.
+
+* Quiescent cavitation on 1024 x 1024 (T = 0.95 T_c, rho_ext = 0.95 rho_L,
+  vapour bubble of radius 20, tau = 0.7, CTU2): FP32 deviation storage
+  against the FP64 stepper after 10^4 steps, rho and u within 1e-5 in the max
+  and in the RMS (u normalised by its largest value).  The FP64 stepper
+  follows the oracle to 1e-13 per step and to 1e-10 over 10^3 steps (parity
+  tests); the oracle itself would take about 15 minutes for these 10^10 node
+  updates.
+* The batched sweep of 32 uneven runs (lattice edges 256..1536, T/T_c in
+  [0.85, 0.97], shear rates 0, 1e-5, 1e-4, FP32 deviation storage), stepped
+  1000 times through one graph-replayed batch: its four smallest runs against
+  the FP64 oracle run on their own, rho and u within 1e-5.
+* The FP64 diagnostics of an FP32-deviation state against the oracle's sums
+  of the same stored values.
+"""
+import numpy as np
+import pytest
+
+import oracle as o
+from gpu_helpers import field_errors, oracle_params
+from paper_1802_01272_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+lbm = pytest.importorskip("paper_1802_01272_amd.lbm")
+
+
+def test_quiescent_cavitation_1024_fp32dev_against_fp64_ten_thousand_steps():
+    w = I.quiescent_bubble(1024, radius=20.0)
+    rho, ux, uy = w.fields()
+    runs = {prec: lbm.Run(lbm.Params.from_workload(w, precision=prec), rho, ux, uy)
+            for prec in (lbm.FP64, lbm.FP32_DEV)}
+    for r in runs.values():
+        r.step(10000)
+    a, b = runs[lbm.FP64].moments(), runs[lbm.FP32_DEV].moments()
+    for r in runs.values():
+        r.close()
+    e = field_errors(b[0], b[1], b[2], a[0], a[1], a[2])
+    print("quiescent cavitation 1024^2, 10^4 steps, FP32-dev vs FP64:", e, "max |u| %.4f" % np.hypot(a[1], a[2]).max())
+    assert e["rho_max"] < 1e-5 and e["u_max"] < 1e-5
+    assert e["rho_rms"] < 1e-5 and e["u_rms"] < 1e-5
+
+
+def test_batched_sweep_smallest_runs_against_oracle():
+    sweep = I.batched_sweep(32, seed=5)
+    params = [lbm.Params.from_workload(w, precision=lbm.FP32_DEV) for w in sweep]
+    fields = [w.fields() for w in sweep]
+    batch = lbm.Batch(params, fields)
+    batch.step(1000, graph_steps=20)
+    order = sorted(range(len(sweep)), key=lambda i: (sweep[i].Lx * sweep[i].Ly, i))[:4]
+    o.set_num_threads(16)
+    for i in order:
+        r, vx, vy = batch.runs[i].moments()
+        op = oracle_params(params[i])
+        rho, ux, uy = fields[i]
+        f = o.run(op, o.init(op, rho, ux, uy), 1000)
+        rr, rx, ry = o.field_moments(op, f)
+        e = field_errors(r, vx, vy, rr, rx, ry)
+        print("sweep run %d (%dx%d, T %.3f, shear %g), 1000 batched steps vs oracle:" % (
+            i, sweep[i].Lx, sweep[i].Ly, sweep[i].T, sweep[i].shear_rate), e)
+        assert e["rho_max"] < 1e-5 and e["u_max"] < 1e-5
+    batch.close()
+
+
+def test_reduce_matches_oracle_fp32dev():
+    w = I.quiescent_bubble(150, radius=25.0)
+    rho, ux, uy = w.fields()
+    p = lbm.Params.from_workload(w, precision=lbm.FP32_DEV)
+    run = lbm.Run(p, rho, ux, uy)
+    run.step(5)
+    f = run.get_f()           # the stored FP32 deviations plus w_k rho_ref, in FP64
+    thr = 0.5 * (w.rho_vapour + w.rho_liquid)
+    st = run.reduce(thr)
+    run.close()
+    ref = o.reduce(oracle_params(p), f, thr)
+    assert st["n_bubble"] == int(ref["n_bubble"]) and st["n_nonfinite"] == 0
+    for k in ("mass", "sx", "sy", "sxx", "sxy", "syy"):
+        assert st[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-9), k
+    for k in ("mom_x", "mom_y"):
+        assert st[k] == pytest.approx(ref[k], abs=1e-10 * ref["mass"]), k
