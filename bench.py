@@ -154,9 +154,11 @@ def copy_probe(args, torch):
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1802_01272_amd", "_lib", "libprobe.so"))
     lib.probe_strip_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 6 + [ctypes.c_void_p]
     lib.probe_flat_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    lib.probe_blocked_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 5 + [ctypes.c_void_p]
     L, reps = args.L, 20
     n = 16 * L * L
-    src = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+    nblk = 16 * ((L + 55) // 56) * 56 * L  # the strip-blocked variants' field
+    src = torch.empty(max(n, nblk), dtype=torch.float32, device="cuda").uniform_()
     dst = torch.empty_like(src)
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
@@ -171,6 +173,13 @@ def copy_probe(args, torch):
                          lambda outw=outw, rows=rows, hy=hy, lds=lds: lib.probe_strip_copy(
                              src.data_ptr(), dst.data_ptr(), L, L, outw, rows, hy, lds, sp)))
     variants.append(("flat_float4", lambda: lib.probe_flat_copy(src.data_ptr(), dst.data_ptr(), n, sp)))
+    # the strip-blocked layout f[block][row][k][56] on 110 blocks (6160 columns)
+    # x L rows: same node count within 0.3%; GB/s scaled to its own bytes below
+    nb = (L + 55) // 56
+    for hy, rows, lds in ((4, 32, 0), (4, 32, 36864), (4, 64, 36864), (0, 32, 36864)):
+        variants.append(("blocked56_rows%d_halo%d%s" % (rows, hy, "_4waves_per_cu" if lds else ""),
+                         lambda hy=hy, rows=rows, lds=lds: lib.probe_blocked_copy(
+                             src.data_ptr(), dst.data_ptr(), nb, L, rows, hy, lds, sp)))
     out = {}
     for name, fn in variants:
         rc = fn()
@@ -185,13 +194,14 @@ def copy_probe(args, torch):
             e1.synchronize()
             times.append(e0.elapsed_time(e1))
         times.sort()
+        b = 2.0 * 4 * nblk if name.startswith("blocked") else algo
         out[name] = {"best_ms": round(times[0], 4), "median_ms": round(times[len(times) // 2], 4),
-                     "GBs_best": round(algo / (times[0] * 1e-3) / 1e9, 1),
-                     "GBs_median": round(algo / (times[len(times) // 2] * 1e-3) / 1e9, 1)}
+                     "GBs_best": round(b / (times[0] * 1e-3) / 1e9, 1),
+                     "GBs_median": round(b / (times[len(times) // 2] * 1e-3) / 1e9, 1)}
         print("[copy-probe] %-34s best %.4f ms (%.0f GB/s), median %.4f ms (%.0f GB/s)"
               % (name, times[0], out[name]["GBs_best"], times[len(times) // 2], out[name]["GBs_median"]),
               file=sys.stderr, flush=True)
-    ok = bool(torch.equal(src.view(16, L, L)[:, :, :64], dst.view(16, L, L)[:, :, :64]))
+    ok = bool(torch.equal(src[:nblk], dst[:nblk]))
     del src, dst
     torch.cuda.empty_cache()
     return {"metric": "copy ceilings of the step's access shape", "unit": "GB/s (algorithmic bytes)",

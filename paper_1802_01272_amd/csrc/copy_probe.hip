@@ -72,6 +72,55 @@ __global__ __launch_bounds__(64) void strip_copy_kernel(const float* __restrict_
     }
 }
 
+// The same strip march on a strip-blocked field: columns in blocks of 56,
+// layout f[block][row][k][56], so the 16 values of a strip's row are one
+// contiguous 3584-byte span; lanes 0-3 and 60-63 read their halo columns from
+// the neighbouring blocks (periodic over nblocks * 56 columns).
+__global__ __launch_bounds__(64) void blocked_copy_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                         int nblocks, int Ly, int rows, int hy, int nwaves,
+                                                         int touch_lds)
+{
+    const int wave = xcd_remap(blockIdx.x, gridDim.x);
+    if (wave >= nwaves) return;
+    if (touch_lds) probe_lds[threadIdx.x] = 0;
+    const int lane = threadIdx.x;
+    const int Lx = nblocks * 56;
+    const int chunk = wave / nblocks, strip = wave - chunk * nblocks;
+    int col = (strip * 56 - 4 + lane) % Lx;
+    if (col < 0) col += Lx;
+    const int blk = col / 56, pos = col - blk * 56;
+    const bool out_lane = lane >= 4 && lane < 60;
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, Ly);
+    const int64_t row_stride = 16 * 56;
+    const int64_t lane_base = (int64_t)blk * Ly * row_stride + pos;
+    const int64_t out_base = (int64_t)strip * Ly * row_stride + (lane - 4);
+    auto row_of = [&](int r) {
+        int rr = r % Ly;
+        return rr < 0 ? rr + Ly : rr;
+    };
+    float v[16], n[16];
+    {
+        const int64_t off = lane_base + (int64_t)row_of(y0 - hy) * row_stride;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = src[off + k * 56];
+    }
+    for (int r = y0 - hy; r < y1 + hy; ++r) {
+        if (r + 1 < y1 + hy) {
+            const int64_t off = lane_base + (int64_t)row_of(r + 1) * row_stride;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) n[k] = src[off + k * 56];
+        }
+        if (r >= y0 && r < y1 && out_lane) {
+            const int64_t off = out_base + (int64_t)r * row_stride;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) dst[off + k * 56] = v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = n[k];
+    }
+}
+
 __global__ __launch_bounds__(256) void flat_copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
                                                         int64_t n4)
 {
@@ -103,6 +152,22 @@ int probe_strip_copy(const float* d_src, float* d_dst, int Lx, int Ly, int outw,
     else
         hipLaunchKernelGGL((strip_copy_kernel<64, 0>), dim3(nwaves), dim3(64), lds_bytes, s, d_src, d_dst, Lx, Ly,
                            rows, halo_y, nstrips, nwaves, lds_bytes > 0 ? 1 : 0);
+    return (int)hipGetLastError();
+}
+
+// Strip copy of a strip-blocked 16-plane FP32 field of nblocks * 56 x Ly
+// nodes (layout f[block][row][k][56]), same march and options as
+// probe_strip_copy with 56 output columns.
+int probe_blocked_copy(const float* d_src, float* d_dst, int nblocks, int Ly, int rows, int halo_y, int lds_bytes,
+                       void* stream)
+{
+    if (!d_src || !d_dst || nblocks < 2 || Ly < 1 || rows < 1 || halo_y < 0 || halo_y > Ly || lds_bytes < 0
+        || lds_bytes > 65536)
+        return (int)hipErrorInvalidValue;
+    const int nchunks = (Ly + rows - 1) / rows;
+    const int nwaves = nblocks * nchunks;
+    hipLaunchKernelGGL(blocked_copy_kernel, dim3(nwaves), dim3(64), lds_bytes, static_cast<hipStream_t>(stream),
+                       d_src, d_dst, nblocks, Ly, rows, halo_y, nwaves, lds_bytes > 0 ? 1 : 0);
     return (int)hipGetLastError();
 }
 
