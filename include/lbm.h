@@ -272,8 +272,14 @@ lbm_status lbm_batch_step(lbm_batch* batch, int64_t nsteps, int32_t graph_steps,
 lbm_status lbm_batch_set_launch(lbm_batch* batch, int32_t rows_per_wave, void* stream);
 
 /* Time candidate rows-per-item values on the batch itself and keep the
- * fastest.  The trials advance every run: by (steps_per_trial + 1) steps per
- * candidate (10 candidates).  sync. */
+ * fastest: first one value for every run (10 candidates), then, for each
+ * class of runs of one lattice shape and boundary condition (largest total
+ * node count first), up to 4 other values for that class alone, kept when
+ * they save more than 1%.  The choice for each class is remembered for the
+ * process: later lbm_batch_init calls start runs of the same shape,
+ * precision, scheme, regularize and boundary from it.  *rows_per_wave
+ * receives the common value of the first pass.  The trials advance every
+ * run: by (steps_per_trial + 1) steps per candidate.  sync. */
 lbm_status lbm_batch_autotune(lbm_batch* batch, int32_t steps_per_trial, void* stream,
                               int32_t* rows_per_wave);
 

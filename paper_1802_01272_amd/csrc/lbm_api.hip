@@ -110,7 +110,6 @@ void fill_coef(const lbm_params* p, StepCoef<R>& c)
     for (int mx = 0; mx < 2; ++mx) {
         const double ax = nu * q[mx], k2x = q[mx] * (1 - ax);
         c.nu_xi[mx] = (R)ax;
-        c.nu_xi_d[mx] = ax;
         for (int my = 0; my < 2; ++my) {
             const double ay = nu * q[my], k2y = q[my] * (1 - ay);
             c.xs1[mx][my] = (R)(-nu * (1 - ay) * k2x);
@@ -224,6 +223,8 @@ bool launch_fits(const lbm_params* p, int wpg)
 std::mutex g_tune_mutex;
 // (Lx, Ly, precision, scheme, regularize, bc_y)
 std::map<std::tuple<int, int, int, int, int, int>, Launch> g_tuned;
+// rows per work item a batch autotune chose for runs of that shape
+std::map<std::tuple<int, int, int, int, int, int>, int> g_batch_tuned;
 
 }  // namespace
 
@@ -866,6 +867,18 @@ extern "C" size_t lbm_batch_workspace_bytes(int32_t n, const lbm_params* params)
 
 namespace {
 
+// forget a captured graph (the work list it baked in has changed)
+void drop_graph(lbm_batch* b)
+{
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->graph_steps = 0;
+    }
+}
+
 template <typename R>
 lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
 {
@@ -884,12 +897,15 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
         br.rows = r.launch.rows_per_wave;
         br.nstrips = (r.p.Lx + STRIP - 1) / STRIP;
         br.plane = plane_of(&r.p);
+        br.walls = r.p.bc_y == LBM_SHEAR_WALLS ? 1 : 0;
+        br.pad_ = 0;
         fill_coef<R>(&r.p, coefs[i]);
         const int nchunks = (r.p.Ly + br.rows - 1) / br.rows;
-        std::vector<BatchItem>& dst = (r.p.bc_y == LBM_SHEAR_WALLS) ? wall_items : items;
+        std::vector<BatchItem>& dst = br.walls ? wall_items : items;
         for (int c = 0; c < nchunks; ++c)
             for (int st = 0; st < br.nstrips; ++st) dst.push_back(BatchItem{i, st, c, 0});
     }
+    // periodic items first, then the items of runs with walls
     b->nitems_periodic = (int32_t)items.size();
     items.insert(items.end(), wall_items.begin(), wall_items.end());
     char* p = base;
@@ -908,21 +924,21 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
 
 lbm_status batch_launch(lbm_batch* b, hipStream_t s)
 {
-    // periodic items first, then the items of runs with shear walls
     const int32_t n_per = b->nitems_periodic, n_wall = b->nitems - b->nitems_periodic;
-    hipError_t e = hipSuccess;
-    for (int walls = 0; walls < 2 && e == hipSuccess; ++walls) {
-        const BatchItem* items = b->d_items + (walls ? n_per : 0);
-        const int32_t n = walls ? n_wall : n_per;
+    const int wpg = (b->precision == LBM_FP32_DEV) ? LBM_PAIR : 1;
+    auto launch = [&](const BatchItem* items, int32_t n, int wmode) -> hipError_t {
         if (b->precision == LBM_FP32_DEV)
-            e = launch_batch_step<float>(static_cast<const BatchRun<float>*>(b->d_runs),
-                                         static_cast<const StepCoef<float>*>(b->d_coefs), items, n, b->cur,
-                                         b->scheme, b->regularize, walls, LBM_PAIR, s);
-        else
-            e = launch_batch_step<double>(static_cast<const BatchRun<double>*>(b->d_runs),
-                                          static_cast<const StepCoef<double>*>(b->d_coefs), items, n, b->cur,
-                                          b->scheme, b->regularize, walls, 1, s);
-    }
+            return launch_batch_step<float>(static_cast<const BatchRun<float>*>(b->d_runs),
+                                            static_cast<const StepCoef<float>*>(b->d_coefs), items, n, b->cur,
+                                            b->scheme, b->regularize, wmode, wpg, s);
+        return launch_batch_step<double>(static_cast<const BatchRun<double>*>(b->d_runs),
+                                         static_cast<const StepCoef<double>*>(b->d_coefs), items, n, b->cur,
+                                         b->scheme, b->regularize, wmode, wpg, s);
+    };
+    // one launch per step; a batch of one boundary kind uses the kernel built
+    // for that kind alone, a mixed batch the kernel that takes each item's
+    // (as fast as two launches, one per kind, on the 32-run sweep)
+    const hipError_t e = launch(b->d_items, b->nitems, n_wall == 0 ? 0 : (n_per == 0 ? 1 : 2));
     if (e != hipSuccess) return hip_fail(e, "batch step launch");
     b->cur ^= 1;
     return LBM_OK;
@@ -977,6 +993,12 @@ lbm_status lbm_batch_init(int32_t n, const lbm_params* params, void* d_ws, size_
         b->runs[i] = *r;
         delete r;
         b->runs[i].batch = b;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mutex);
+            const lbm_params& q = params[i];
+            auto it = g_batch_tuned.find({q.Lx, q.Ly, q.precision, q.scheme, q.regularize, q.bc_y});
+            if (it != g_batch_tuned.end()) b->runs[i].launch.rows_per_wave = it->second;
+        }
         p += run_bytes(&params[i]);
     }
     lbm_status st = (b->precision == LBM_FP32_DEV) ? batch_tables<float>(b, p, s) : batch_tables<double>(b, p, s);
@@ -1061,13 +1083,7 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t rows_per_wave, void* strea
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipStreamSynchronize(s), "batch set launch");
     for (auto& r : b->runs) r.launch.rows_per_wave = rows_per_wave;
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
-        b->graph_steps = 0;
-    }
+    drop_graph(b);
     char* base = static_cast<char*>(b->d_runs);
     return (b->precision == LBM_FP32_DEV) ? batch_tables<float>(b, base, s) : batch_tables<double>(b, base, s);
 }
@@ -1077,37 +1093,90 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps_per_trial, void* strea
     if (!b || !rows_per_wave) return fail(LBM_EINVAL, "null argument");
     if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int rows_c[] = {16, 24, 32, 40, 48, 64, 96, 128, 192, 256};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "batch autotune");
     HIP_TRY(hipEventCreate(&e1), "batch autotune");
-    double best = 1e300;
-    int best_rows = rows_c[0];
-    lbm_status st = LBM_OK;
-    for (int rows : rows_c) {
-        st = lbm_batch_set_launch(b, rows, stream);
-        if (st != LBM_OK) break;
-        st = lbm_batch_step(b, 1, 0, stream);
-        if (st != LBM_OK) break;
-        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(LBM_EDEVICE, "batch autotune event"); break; }
+    // device time of steps_per_trial steps with the batch's current work list
+    // (one untimed step first)
+    auto trial = [&](double* ms_out) -> lbm_status {
+        lbm_status st = lbm_batch_step(b, 1, 0, stream);
+        if (st != LBM_OK) return st;
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(LBM_EDEVICE, "batch autotune event");
         st = lbm_batch_step(b, steps_per_trial, 0, stream);
-        if (st != LBM_OK) break;
+        if (st != LBM_OK) return st;
         float ms = 0;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess
-            || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            st = fail(LBM_EDEVICE, "batch autotune timing");
-            break;
-        }
+            || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return fail(LBM_EDEVICE, "batch autotune timing");
+        *ms_out = ms;
+        return LBM_OK;
+    };
+    // rebuild the work list with the rows now set on each member
+    auto retable = [&]() -> lbm_status {
+        HIP_TRY(hipStreamSynchronize(s), "batch autotune");
+        drop_graph(b);
+        char* base = static_cast<char*>(b->d_runs);
+        return (b->precision == LBM_FP32_DEV) ? batch_tables<float>(b, base, s) : batch_tables<double>(b, base, s);
+    };
+    lbm_status st = LBM_OK;
+    // 1. one rows value for every run
+    const int rows_c[] = {16, 24, 32, 40, 48, 64, 96, 128, 192, 256};
+    double best = 1e300;
+    int best_rows = rows_c[0];
+    for (int rows : rows_c) {
+        double ms = 0;
+        st = lbm_batch_set_launch(b, rows, stream);
+        if (st == LBM_OK) st = trial(&ms);
+        if (st != LBM_OK) break;
         if (ms < best) {
             best = ms;
             best_rows = rows;
         }
     }
+    if (st == LBM_OK) st = lbm_batch_set_launch(b, best_rows, stream);
+    // 2. then each class of runs (lattice shape and boundary), largest total
+    // node count first, tries other rows values with the rest fixed and keeps
+    // one that is faster by more than 1%
+    std::map<std::tuple<int, int, int>, int64_t> nodes_of;
+    for (auto& r : b->runs) nodes_of[{r.p.Lx, r.p.Ly, r.p.bc_y}] += (int64_t)r.p.Lx * r.p.Ly;
+    std::vector<std::pair<int64_t, std::tuple<int, int, int>>> classes;
+    for (auto& kv : nodes_of) classes.push_back({kv.second, kv.first});
+    std::sort(classes.begin(), classes.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    if (st == LBM_OK && classes.size() > 1) st = trial(&best);
+    for (size_t c = 0; st == LBM_OK && c < classes.size(); ++c) {
+        const auto key = classes[c].second;
+        auto set_rows = [&](int rows) {
+            for (auto& r : b->runs)
+                if (std::make_tuple(r.p.Lx, r.p.Ly, r.p.bc_y) == key) r.launch.rows_per_wave = rows;
+        };
+        int keep = best_rows;
+        for (int rows : {best_rows / 2, (3 * best_rows) / 4, (3 * best_rows) / 2, 2 * best_rows}) {
+            if (rows < 8 || rows == best_rows) continue;
+            double ms = 0;
+            set_rows(rows);
+            st = retable();
+            if (st == LBM_OK) st = trial(&ms);
+            if (st != LBM_OK) break;
+            if (ms < 0.99 * best) {
+                best = ms;
+                keep = rows;
+            }
+        }
+        set_rows(keep);
+        if (st == LBM_OK) st = retable();
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != LBM_OK) return st;
+    // batches created later in the process start from these shapes
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        for (auto& r : b->runs)
+            g_batch_tuned[{r.p.Lx, r.p.Ly, r.p.precision, r.p.scheme, r.p.regularize, r.p.bc_y}] =
+                r.launch.rows_per_wave;
+    }
     *rows_per_wave = best_rows;
-    return lbm_batch_set_launch(b, best_rows, stream);
+    return LBM_OK;
 }
 
 void lbm_batch_destroy(lbm_batch* b)

@@ -63,8 +63,6 @@ struct StepCoef {
     R ys2[2][2];   // -nu  nu |xi_x|      k2[my]   weight of dY at the column upwind in x
     R ghost_lo[16], ghost_hi[16];          // stored values of the two wall ghost-row states
     // node-local terms, always FP64
-    double nu_xi_d[2];  // nu |xi| in FP64: the CTU1 weights of the FP64 sum that
-                        // FP32 storage uses
     double rho0;        // rho_ref (deviation storage) or 0
     double T, Tm1;      // T and T - 1
     double a_vdw, b_vdw;
@@ -115,6 +113,8 @@ struct BatchRun {
     int32_t Lx, Ly;
     int32_t rows, nstrips;
     int64_t plane;
+    int32_t walls;      // shear walls (1) or periodic in y (0)
+    int32_t pad_;
 };
 
 // Launch shape of the step kernel.
@@ -127,10 +127,12 @@ struct Launch {
 template <typename R>
 hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int walls, int waves_per_group,
                        hipStream_t s);
+// wmode: 0 = every item periodic, 1 = every item with walls, 2 = mixed (each
+// item takes its run's boundary)
 template <typename R>
 hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coefs,
                              const BatchItem* d_items, int32_t nitems, int32_t cur, int scheme,
-                             int regularize, int walls, int waves_per_group, hipStream_t s);
+                             int regularize, int wmode, int waves_per_group, hipStream_t s);
 template <typename R>
 hipError_t launch_init(R* f, const StepCoef<R>* coef, const double* rho, const double* ux,
                        const double* uy, int64_t n, int64_t plane, hipStream_t s);

@@ -291,7 +291,10 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     // speed by a few 1e-8 every step, which moves a growing bubble's interface
     // coherently (after 10^4 steps on a 1024^2 cavitation run, rho and u
     // errors at the interface 3-4x larger).  The CTU2 corrections stay FP32.
-    constexpr bool SUM64 = sizeof(R) == 4;
+    // The regularized CTU2 kernel keeps the FP32 sum with the two FP32
+    // weights: the FP64 carries push its advecting wavefront past 256
+    // registers (spills to scratch).
+    constexpr bool SUM64 = sizeof(R) == 4 && (SCHEME == 1 || !REG);
     using CD = std::conditional_t<SUM64, N, R>;
     CD cD1[16];
     R cY[16], cdX[16], cR2[16];
@@ -394,7 +397,10 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
             // repeats step after step).  D1 of the row that is reused one row
             // later is carried in cD1.
             const R ax = C->nu_xi[MX], ay = C->nu_xi[MY];
-            const N axd = C->nu_xi_d[MX], ayd = C->nu_xi_d[MY];
+            // FP64 weights nu |xi| (from values the kernel holds anyway; a
+            // separate FP64 table in the coefficient block pushed the
+            // advecting wavefront past 256 registers)
+            const N axd = C->dt * C->inv_ds * (MX ? QL : QS), ayd = C->dt * C->inv_ds * (MY ? QL : QS);
             R inc = 0;    // CTU1 part (FOLD: f + CTU1 part)
             N inc64 = 0;  // SUM64: CTU1 part, plus f without walls
             R corr = 0;   // CTU2 corrections
@@ -809,7 +815,23 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void p
     }
 }
 
-template <typename R, int SCHEME, bool REG, bool WALLS>
+// Boundary of a batched launch: WMODE 0 (all items periodic) or 1 (all with
+// walls) fixes the body at compile time; WMODE 2 covers both kinds in one
+// grid, each work item taking the body of its run's boundary on a branch that
+// is uniform over the workgroup (the item and its run are scalar).  Every run
+// computes exactly what its single-run kernel computes.
+template <int WMODE, typename F>
+__device__ __forceinline__ void with_walls(int walls, F&& f)
+{
+    if constexpr (WMODE == 2) {
+        if (walls) f(std::integral_constant<bool, true>{});
+        else f(std::integral_constant<bool, false>{});
+    } else {
+        f(std::integral_constant<bool, WMODE == 1>{});
+    }
+}
+
+template <typename R, int SCHEME, bool REG, int WMODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::value))) void batch_step_kernel(const BatchRun<R>* __restrict__ runs,
                                                          const StepCoef<R>* __restrict__ coefs,
                                                          const BatchItem* __restrict__ items,
@@ -826,12 +848,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEU<
     R* const fa = run.f[0];
     R* const fb = run.f[1];
     const uint32_t seed = step_seed<R>(run.seq, cur, it.strip == 0 && it.chunk == 0);
-    strip_step<R, SCHEME, REG, WALLS>(cur ? fb : fa, cur ? fa : fb, coefs + it.run,
-                                      run.Lx, run.Ly, run.plane, it.strip, y0, y1, wave_lds(), seed);
+    with_walls<WMODE>(run.walls, [&](auto wl) {
+        strip_step<R, SCHEME, REG, decltype(wl)::value>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx, run.Ly,
+                                                        run.plane, it.strip, y0, y1, wave_lds(), seed);
+    });
 }
 
 // The batched launch with a pair of wavefronts per work item (FP32 storage).
-template <typename R, int SCHEME, bool REG, bool WALLS>
+template <typename R, int SCHEME, bool REG, int WMODE>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void batch_pair_step_kernel(
     const BatchRun<R>* __restrict__ runs, const StepCoef<R>* __restrict__ coefs, const BatchItem* __restrict__ items,
     int nitems, int cur)
@@ -847,14 +871,17 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void b
     R* const fb = run.f[1];
     double* const pend = reinterpret_cast<double*>(step_lds);  // PAIR_STEP_LDS bytes
     double* const dsl = pend + PENDING_ROWS * 16 * WAVE;
-    if (role == 0) {
-        strip_step<R, SCHEME, REG, WALLS, 1>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx, run.Ly,
-                                             run.plane, it.strip, y0, y1, pend, 0u, dsl);
-    } else {
-        const uint32_t seed = step_seed<R>(run.seq, cur, it.strip == 0 && it.chunk == 0);
-        strip_step<R, SCHEME, REG, WALLS, 2>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx, run.Ly,
-                                             run.plane, it.strip, y0, y1, pend, seed, dsl);
-    }
+    with_walls<WMODE>(run.walls, [&](auto wl) {
+        constexpr bool WL = decltype(wl)::value;
+        if (role == 0) {
+            strip_step<R, SCHEME, REG, WL, 1>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx, run.Ly,
+                                              run.plane, it.strip, y0, y1, pend, 0u, dsl);
+        } else {
+            const uint32_t seed = step_seed<R>(run.seq, cur, it.strip == 0 && it.chunk == 0);
+            strip_step<R, SCHEME, REG, WL, 2>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx, run.Ly,
+                                              run.plane, it.strip, y0, y1, pend, seed, dsl);
+        }
+    });
 }
 
 // ----------------------------------------------------------------------------
@@ -1026,69 +1053,102 @@ template <typename R>
 hipError_t launch_step(const RunView<R>& rv, int scheme, int regularize, int walls, int wpg, hipStream_t s)
 {
     // wpg = LBM_PAIR: one workgroup of two wavefronts per strip and chunk
-    // (FP32 storage); else wpg independent wavefronts per workgroup
+    // (FP32 storage only: the pair kernels are instantiated for FP32 alone);
+    // else wpg independent wavefronts per workgroup
     const bool pair = wpg == LBM_PAIR;
-    if (pair && sizeof(R) != 4) return hipErrorInvalidValue;
-    if (pair) wpg = 1;
     const int nchunks = (rv.Ly + rv.rows - 1) / rv.rows;
     const int nwaves = rv.nstrips * nchunks;  // pairs with LBM_PAIR
+#define LBM_DISPATCH(LAUNCH)                       \
+    if (scheme == 1) {                             \
+        if (regularize) {                          \
+            if (walls) LAUNCH(1, true, true);      \
+            else LAUNCH(1, true, false);           \
+        } else {                                   \
+            if (walls) LAUNCH(1, false, true);     \
+            else LAUNCH(1, false, false);          \
+        }                                          \
+    } else {                                       \
+        if (regularize) {                          \
+            if (walls) LAUNCH(2, true, true);      \
+            else LAUNCH(2, true, false);           \
+        } else {                                   \
+            if (walls) LAUNCH(2, false, true);     \
+            else LAUNCH(2, false, false);          \
+        }                                          \
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (pair) {
+#define LBM_PAIR_LAUNCH(SC, RG, WL)                                                                         \
+    hipLaunchKernelGGL((pair_step_kernel<R, SC, RG, WL>), dim3(nwaves), dim3(2 * WAVE), PAIR_STEP_LDS, s, \
+                       rv.f_in, rv.f_out, rv.coef, rv.seq, rv.cur, rv.Lx, rv.Ly, rv.plane, rv.rows,      \
+                       rv.nstrips, nwaves)
+            LBM_DISPATCH(LBM_PAIR_LAUNCH)
+#undef LBM_PAIR_LAUNCH
+            return hipGetLastError();
+        }
+    }
+    if (pair) return hipErrorInvalidValue;
     const int nblocks = (nwaves + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
     const size_t lds = wpg * STEP_LDS_PER_WAVE;
-#define LBM_LAUNCH(SC, RG, WL)                                                                                 \
-    if (pair)                                                                                                  \
-        hipLaunchKernelGGL((pair_step_kernel<R, SC, RG, WL>), dim3(nwaves), dim3(2 * WAVE), PAIR_STEP_LDS, s, \
-                           rv.f_in, rv.f_out, rv.coef, rv.seq, rv.cur, rv.Lx, rv.Ly, rv.plane, rv.rows,      \
-                           rv.nstrips, nwaves);                                                               \
-    else                                                                                                       \
-        hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, lds, s, rv.f_in, rv.f_out, rv.coef,     \
-                           rv.seq, rv.cur, rv.Lx, rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
-#define LBM_LAUNCH_W(SC, RG)          \
-    if (walls) LBM_LAUNCH(SC, RG, true); \
-    else LBM_LAUNCH(SC, RG, false)
-    if (scheme == 1) {
-        if (regularize) LBM_LAUNCH_W(1, true);
-        else LBM_LAUNCH_W(1, false);
-    } else {
-        if (regularize) LBM_LAUNCH_W(2, true);
-        else LBM_LAUNCH_W(2, false);
-    }
-#undef LBM_LAUNCH_W
-#undef LBM_LAUNCH
+#define LBM_SINGLE_LAUNCH(SC, RG, WL)                                                                          \
+    hipLaunchKernelGGL((step_kernel<R, SC, RG, WL>), grid, block, lds, s, rv.f_in, rv.f_out, rv.coef, rv.seq, \
+                       rv.cur, rv.Lx, rv.Ly, rv.plane, rv.rows, rv.nstrips, nwaves)
+    LBM_DISPATCH(LBM_SINGLE_LAUNCH)
+#undef LBM_SINGLE_LAUNCH
+#undef LBM_DISPATCH
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coefs, const BatchItem* d_items,
-                             int32_t nitems, int32_t cur, int scheme, int regularize, int walls, int wpg,
+                             int32_t nitems, int32_t cur, int scheme, int regularize, int wmode, int wpg,
                              hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
+    if (wmode < 0 || wmode > 2) return hipErrorInvalidValue;
     const bool pair = wpg == LBM_PAIR;
-    if (pair && sizeof(R) != 4) return hipErrorInvalidValue;
-    if (pair) wpg = 1;
+#define LBM_DISPATCH(LAUNCH)                                         \
+    if (scheme == 1) {                                               \
+        if (regularize) {                                            \
+            if (wmode == 0) LAUNCH(1, true, 0);                      \
+            else if (wmode == 1) LAUNCH(1, true, 1);                 \
+            else LAUNCH(1, true, 2);                                 \
+        } else {                                                     \
+            if (wmode == 0) LAUNCH(1, false, 0);                     \
+            else if (wmode == 1) LAUNCH(1, false, 1);                \
+            else LAUNCH(1, false, 2);                                \
+        }                                                            \
+    } else {                                                         \
+        if (regularize) {                                            \
+            if (wmode == 0) LAUNCH(2, true, 0);                      \
+            else if (wmode == 1) LAUNCH(2, true, 1);                 \
+            else LAUNCH(2, true, 2);                                 \
+        } else {                                                     \
+            if (wmode == 0) LAUNCH(2, false, 0);                     \
+            else if (wmode == 1) LAUNCH(2, false, 1);                \
+            else LAUNCH(2, false, 2);                                \
+        }                                                            \
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (pair) {
+#define LBM_PAIR_LAUNCH(SC, RG, WM)                                                                          \
+    hipLaunchKernelGGL((batch_pair_step_kernel<R, SC, RG, WM>), dim3(nitems), dim3(2 * WAVE), PAIR_STEP_LDS, s, \
+                       d_runs, d_coefs, d_items, nitems, cur)
+            LBM_DISPATCH(LBM_PAIR_LAUNCH)
+#undef LBM_PAIR_LAUNCH
+            return hipGetLastError();
+        }
+    }
+    if (pair) return hipErrorInvalidValue;
     const int nblocks = (nitems + wpg - 1) / wpg;
     const dim3 grid(nblocks), block(WAVE * wpg);
     const size_t lds = wpg * STEP_LDS_PER_WAVE;
-#define LBM_LAUNCH(SC, RG, WL)                                                                                  \
-    if (pair)                                                                                                   \
-        hipLaunchKernelGGL((batch_pair_step_kernel<R, SC, RG, WL>), dim3(nitems), dim3(2 * WAVE), PAIR_STEP_LDS, \
-                           s, d_runs, d_coefs, d_items, nitems, cur);                                           \
-    else                                                                                                        \
-        hipLaunchKernelGGL((batch_step_kernel<R, SC, RG, WL>), grid, block, lds, s, d_runs, d_coefs, d_items,   \
-                           nitems, cur)
-#define LBM_LAUNCH_W(SC, RG)          \
-    if (walls) LBM_LAUNCH(SC, RG, true); \
-    else LBM_LAUNCH(SC, RG, false)
-    if (scheme == 1) {
-        if (regularize) LBM_LAUNCH_W(1, true);
-        else LBM_LAUNCH_W(1, false);
-    } else {
-        if (regularize) LBM_LAUNCH_W(2, true);
-        else LBM_LAUNCH_W(2, false);
-    }
-#undef LBM_LAUNCH_W
-#undef LBM_LAUNCH
+#define LBM_SINGLE_LAUNCH(SC, RG, WM) \
+    hipLaunchKernelGGL((batch_step_kernel<R, SC, RG, WM>), grid, block, lds, s, d_runs, d_coefs, d_items, nitems, cur)
+    LBM_DISPATCH(LBM_SINGLE_LAUNCH)
+#undef LBM_SINGLE_LAUNCH
+#undef LBM_DISPATCH
     return hipGetLastError();
 }
 

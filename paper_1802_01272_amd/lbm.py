@@ -386,8 +386,10 @@ class Batch:
         _check(LIB.lbm_batch_set_launch(self.handle, int(rows_per_wave), _stream_handle(self.torch, stream)))
 
     def autotune(self, steps_per_trial: int = 3, stream=None) -> int:
-        """Pick the rows per work item on the batch itself; advances every run
-        by 10 * (steps_per_trial + 1) steps."""
+        """Pick the rows per work item on the batch itself, one common value
+        and then one per class of runs of a shape and boundary (remembered for
+        later batches); advances every run by (steps_per_trial + 1) steps per
+        trial, 10 to 11 + 4 * classes trials.  Returns the common value."""
         rows = ctypes.c_int32()
         _check(LIB.lbm_batch_autotune(self.handle, int(steps_per_trial), _stream_handle(self.torch, stream),
                                       ctypes.byref(rows)))

@@ -440,9 +440,26 @@ def test_batch_set_launch_and_autotune():
         assert np.array_equal(m.get_f(), ref)
     rows = batch.autotune(1)
     assert rows in (16, 24, 32, 40, 48, 64, 96, 128, 192, 256)
-    assert all(m.step_count == 3 + 10 * 2 for m in batch.runs)
+    # 10 common candidates, one re-timing, up to 4 per class (two classes)
+    counts = {m.step_count for m in batch.runs}
+    assert len(counts) == 1 and 3 + 2 * 11 <= counts.pop() <= 3 + 2 * 19
+    per_run = [m.get_launch()[0] for m in batch.runs]
+    assert all(r in (rows, rows // 2, (3 * rows) // 4, (3 * rows) // 2, 2 * rows) for r in per_run)
     st = batch.runs[0].reduce(1.0)
     assert st["n_nonfinite"] == 0
+    # the per-class choice stays bit-exact against single runs with that shape
+    states = [random_state(p, 97 + i) for i, p in enumerate(specs)]
+    singles = [gpu_step_from(p, f, nsteps=3, launch=(r, 1)) for p, f, r in zip(specs, states, per_run)]
+    for m, f in zip(batch.runs, states):
+        m.set_f(f)
+    batch.step(3, graph_steps=3)
+    for m, ref in zip(batch.runs, singles):
+        assert np.array_equal(m.get_f(), ref)
+    batch.close()
+    # a later batch of the same shapes starts from the tuned values
+    again = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
+    assert [m.get_launch()[0] for m in again.runs] == per_run
+    again.close()
 
 
 def test_rejects_bad_parameters():
