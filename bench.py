@@ -34,26 +34,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_valu(kernel_key, launch):
-    """VALU instructions per launch (rocprofv3 SQ_INSTS_VALU) from the
-    committed counter summary, if it was taken on the current kernel source
-    and in this launch shape (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    try:
-        with open(path) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    entry = t.get(kernel_key)
-    if (not entry or entry.get("source_hash") != kernel_source_hash()
-            or list(entry.get("launch", [])) != list(launch)):
-        return None
-    return entry.get("valu_per_launch")
-
-
-def measured_traffic(kernel_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
+def _profiled(kernel_key, launch):
+    """The committed rocprofv3 counter summary (profiles/traffic.json) of a
+    step kernel in one launch shape, if it was taken on the current kernel
+    source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -63,13 +47,40 @@ def measured_traffic(kernel_key):
     entry = t.get(kernel_key)
     if not entry or entry.get("source_hash") != kernel_source_hash():
         return None
-    return entry.get("bytes_per_launch")
+    return entry.get("by_launch", {}).get("%d,%d" % tuple(launch))
 
 
-def cpu_baseline(workload, rho, ux, uy, budget_s=12.0, rows=256, max_steps=20):
+def measured_valu(kernel_key, launch):
+    """VALU instructions per launch (rocprofv3 SQ_INSTS_VALU), or None."""
+    e = _profiled(kernel_key, launch)
+    return e.get("valu_per_launch") if e else None
+
+
+def measured_traffic(kernel_key, launch):
+    """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy's reading), or None."""
+    e = _profiled(kernel_key, launch)
+    return e.get("bytes_per_launch") if e else None
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(workload, rho, ux, uy, budget_s=12.0, rows=256, max_steps=20, single_budget_s=6.0):
     """The oracle (FP64 CPU reference, OpenMP) timed on a band of `rows` full
     rows of the workload's initial state (periodic), one step at a time until
-    about budget_s seconds of work."""
+    about budget_s seconds of work on all its threads, then again on one
+    thread for about single_budget_s seconds."""
     import numpy as np
     import oracle as o
     p = o.Params(Lx=workload.Lx, Ly=rows, ds=workload.ds, dt=workload.dt, tau=workload.tau, T=workload.T,
@@ -87,8 +98,23 @@ def cpu_baseline(workload, rho, ux, uy, budget_s=12.0, rows=256, max_steps=20):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": round(p.Lx * p.Ly * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": o.num_threads(),
-            "kind": "oracle",
+    threads = o.num_threads()
+    # the same band on one thread
+    o.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        steps1 = 0
+        while steps1 < max_steps:
+            f = o.step(p, f)
+            steps1 += 1
+            if time.perf_counter() - t1 > single_budget_s:
+                break
+        dt1 = time.perf_counter() - t1
+    finally:
+        o.set_num_threads(threads)
+    return {"value": round(p.Lx * p.Ly * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle", "cpu": cpu_model(),
+            "single_thread": {"value": round(p.Lx * p.Ly * steps1 / dt1 / 1e6, 3), "unit": "MLUPS", "steps": steps1},
             "sample": "%d x %d band of the workload's initial state (periodic), %d steps, FP64" % (p.Lx, rows, steps)}
 
 
@@ -142,6 +168,45 @@ def batched_sweep(args, torch, I, lbm, graph_steps=20):
                        "storage": "FP32 f - w rho_ref"},
             "sequential": {"value": round(seq, 1), "ms_per_step": round(ms_seq / steps, 5)},
             "speedup_batched_over_sequential": round(ms_seq / ms_batch, 3)}
+
+
+def batched_tail(args, torch, I, lbm, graph_steps=20, copies=(1, 2, 4)):
+    """What the launch boundary costs the batched sweep: the 32-run sweep, and
+    the same sweep held 2 and 4 times over in one batch (every run repeated),
+    each autotuned on itself and timed the same way.  A straight-line fit of
+    the time per step against the number of copies n, T(n) = c + n m, splits
+    a step into the part that grows with the work (m per copy) and the part
+    that does not (c): the launch itself and the tail in which the step's last
+    items run on a partly idle chip, which a persistent kernel without a
+    launch per step could at best remove."""
+    import numpy as np
+    sweep = I.batched_sweep(32, seed=5)
+    params = [lbm.Params.from_workload(w, precision=lbm.FP32_DEV) for w in sweep]
+    fields = [w.fields() for w in sweep]
+    nodes = sum(w.Lx * w.Ly for w in sweep)
+    rows = {}
+    for n in copies:
+        batch = lbm.Batch(params * n, fields * n)
+        batch.autotune(2)
+        batch.step(args.warmup, graph_steps=graph_steps)
+        ms = timed_steps(torch, lambda k: batch.step(k, graph_steps=graph_steps), args.steps) / args.steps
+        rows[n] = ms
+        batch.close()
+        del batch
+        torch.cuda.empty_cache()
+        print("[bench] batched sweep x%d: %.5f ms per step" % (n, ms), file=sys.stderr, flush=True)
+    ns = np.array(sorted(rows), dtype=float)
+    ts = np.array([rows[int(n)] for n in ns])
+    m, c = np.polyfit(ns, ts, 1)
+    return {"metric": "batched sweep: per-step time against copies of the sweep held in one batch",
+            "value": round(float(c) / rows[1], 4), "unit": "fixed part of one copy's step",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "batched_sweep_32", "runs": len(sweep), "nodes": nodes,
+                       "copies": [int(n) for n in ns], "graph_steps": graph_steps},
+            "ms_per_step": {str(int(n)): round(rows[int(n)], 5) for n in ns},
+            "fit": {"fixed_ms": round(float(c), 5), "per_copy_ms": round(float(m), 5),
+                    "marginal_mlups": round(nodes / (float(m) * 1e-3) / 1e6, 1)}}
 
 
 def copy_probe(args, torch):
@@ -229,6 +294,10 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="instead of the 6144^2 lattice: the 32-run sweep of uneven lattices in one batched, "
                          "graph-captured launch per step against the same runs stepped one after another")
+    ap.add_argument("--batched-tail", action="store_true",
+                    help="instead of the 6144^2 lattice: the 32-run sweep held 1, 2 and 4 times over in one batch, "
+                         "splitting the batched step's time into a part that grows with the work and a fixed part "
+                         "(launch and tail)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="instead of the stepper: plain copies of the FP32 field in the step's access shape and "
                          "simpler ones (memory-side ceilings, GB/s of algorithmic bytes)")
@@ -248,6 +317,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batched:
         print(json.dumps(batched_sweep(args, torch, I, lbm)), flush=True)
+        return
+    if args.batched_tail:
+        print(json.dumps(batched_tail(args, torch, I, lbm)), flush=True)
         return
     if args.copy_probe:
         print(json.dumps(copy_probe(args, torch)), flush=True)
@@ -330,7 +402,8 @@ def main():
                    "storage": "FP32 f - w rho_ref", "rho_ref": round(w.rho_ref, 6), "launch": list(f32["launch"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic("step_fp32dev_ctu%d%s_%d" % (w.scheme, "_reg" if w.regularize else "", w.Lx))},
+                     "traffic": measured_traffic("step_fp32dev_ctu%d%s_%d" % (w.scheme, "_reg" if w.regularize else "", w.Lx),
+                                                 f32["launch"])},
     }
     # the second bound of the same kernel: VALU issue (one wavefront
     # instruction per SIMD every 4 cycles, 1024 SIMDs at 2.4 GHz)
@@ -345,7 +418,8 @@ def main():
         line["fp64"] = {"mlups": round(f64["mlups"], 1), "ms_per_step": round(f64["ms_per_step"], 5),
                         "achieved_GBs": round(ach64, 1), "frac": round(ach64 / PEAK_HBM_GBS, 4),
                         "launch": list(f64["launch"]),
-                        "traffic": measured_traffic("step_fp64_ctu%d%s_%d" % (w.scheme, "_reg" if w.regularize else "", w.Lx))}
+                        "traffic": measured_traffic("step_fp64_ctu%d%s_%d" % (w.scheme, "_reg" if w.regularize else "", w.Lx),
+                                                    f64["launch"])}
         line["speedup_fp32dev_over_fp64"] = round(f64["ms_per_step"] / f32["ms_per_step"], 3)
     if err:
         line["error_fp32dev"] = err
