@@ -144,8 +144,11 @@ def batched_sweep(args, torch, I, lbm, graph_steps=20):
     steps = args.steps
     batch = lbm.Batch(params, fields)
     rows = batch.autotune(2)
-    batch.step(args.warmup, graph_steps=graph_steps)
+    mode = "persistent" if batch.mode == lbm.BATCH_PERSISTENT else "per_step"
+    # the warm-up captures and replays the graph, so no capture is timed
+    batch.step(max(args.warmup, 2 * graph_steps + 1), graph_steps=graph_steps)
     ms_batch = timed_steps(torch, lambda n: batch.step(n, graph_steps=graph_steps), steps)
+    batch.sync_status()
     batch.close()
     del batch
     torch.cuda.empty_cache()
@@ -165,6 +168,7 @@ def batched_sweep(args, torch, I, lbm, graph_steps=20):
             "data": "synthetic",
             "config": {"workload": "batched_sweep_32", "runs": len(sweep), "nodes": nodes,
                        "edges": sorted({w.Lx for w in sweep}), "rows_per_wave": rows, "graph_steps": graph_steps,
+                       "mode": mode,
                        "storage": "FP32 f - w rho_ref"},
             "sequential": {"value": round(seq, 1), "ms_per_step": round(ms_seq / steps, 5)},
             "speedup_batched_over_sequential": round(ms_seq / ms_batch, 3)}
@@ -173,40 +177,53 @@ def batched_sweep(args, torch, I, lbm, graph_steps=20):
 def batched_tail(args, torch, I, lbm, graph_steps=20, copies=(1, 2, 4)):
     """What the launch boundary costs the batched sweep: the 32-run sweep, and
     the same sweep held 2 and 4 times over in one batch (every run repeated),
-    each autotuned on itself and timed the same way.  A straight-line fit of
-    the time per step against the number of copies n, T(n) = c + n m, splits
-    a step into the part that grows with the work (m per copy) and the part
-    that does not (c): the launch itself and the tail in which the step's last
-    items run on a partly idle chip, which a persistent kernel without a
-    launch per step could at best remove."""
+    each autotuned on itself, then timed in both launch modes with the tuned
+    rows: one launch per step, and the persistent launch (no boundary
+    between steps).  A straight-line fit of the time per step against the
+    number of copies n, T(n) = c + n m, splits a step into the part that
+    grows with the work (m per copy) and the part that does not (c): the
+    launch itself and the tail in which the step's last items run on a
+    partly idle chip."""
     import numpy as np
     sweep = I.batched_sweep(32, seed=5)
     params = [lbm.Params.from_workload(w, precision=lbm.FP32_DEV) for w in sweep]
     fields = [w.fields() for w in sweep]
     nodes = sum(w.Lx * w.Ly for w in sweep)
-    rows = {}
+    modes = {"per_step": lbm.BATCH_PER_STEP, "persistent": lbm.BATCH_PERSISTENT}
+    ms = {name: {} for name in modes}
+    tuned = {}
     for n in copies:
         batch = lbm.Batch(params * n, fields * n)
         batch.autotune(2)
-        batch.step(args.warmup, graph_steps=graph_steps)
-        ms = timed_steps(torch, lambda k: batch.step(k, graph_steps=graph_steps), args.steps) / args.steps
-        rows[n] = ms
+        tuned[n] = {"mode": [k for k, v in modes.items() if v == batch.mode][0],
+                    "rows": sorted({m.get_launch()[0] for m in batch.runs})}
+        for name, mode in modes.items():
+            batch.set_mode(mode)
+            batch.step(max(args.warmup, 2 * graph_steps + 1), graph_steps=graph_steps)
+            t = timed_steps(torch, lambda k: batch.step(k, graph_steps=graph_steps), args.steps) / args.steps
+            batch.sync_status()
+            ms[name][n] = t
+            print("[bench] batched sweep x%d, %s: %.5f ms per step" % (n, name, t), file=sys.stderr, flush=True)
         batch.close()
         del batch
         torch.cuda.empty_cache()
-        print("[bench] batched sweep x%d: %.5f ms per step" % (n, ms), file=sys.stderr, flush=True)
-    ns = np.array(sorted(rows), dtype=float)
-    ts = np.array([rows[int(n)] for n in ns])
-    m, c = np.polyfit(ns, ts, 1)
+    fits = {}
+    for name in modes:
+        ns = np.array(sorted(ms[name]), dtype=float)
+        ts = np.array([ms[name][int(n)] for n in ns])
+        m, c = np.polyfit(ns, ts, 1)
+        fits[name] = {"fixed_ms": round(float(c), 5), "per_copy_ms": round(float(m), 5),
+                      "marginal_mlups": round(nodes / (float(m) * 1e-3) / 1e6, 1),
+                      "ms_per_step": {str(n): round(ms[name][n], 5) for n in sorted(ms[name])},
+                      "mlups": {str(n): round(n * nodes / (ms[name][n] * 1e-3) / 1e6, 1) for n in sorted(ms[name])}}
     return {"metric": "batched sweep: per-step time against copies of the sweep held in one batch",
-            "value": round(float(c) / rows[1], 4), "unit": "fixed part of one copy's step",
+            "value": round(fits["per_step"]["fixed_ms"] / ms["per_step"][1], 4),
+            "unit": "fixed part of one copy's step (one launch per step)",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": "batched_sweep_32", "runs": len(sweep), "nodes": nodes,
-                       "copies": [int(n) for n in ns], "graph_steps": graph_steps},
-            "ms_per_step": {str(int(n)): round(rows[int(n)], 5) for n in ns},
-            "fit": {"fixed_ms": round(float(c), 5), "per_copy_ms": round(float(m), 5),
-                    "marginal_mlups": round(nodes / (float(m) * 1e-3) / 1e6, 1)}}
+                       "copies": list(copies), "graph_steps": graph_steps, "autotuned": tuned},
+            "modes": fits}
 
 
 def copy_probe(args, torch):
@@ -287,6 +304,9 @@ def main():
                     help="fixed launch shape ROWS,WAVES (rows per strip and workgroup; wavefronts per workgroup, "
                          "or 0 for a pair of wavefronts per strip) of the FP32 stepper instead of the autotuner's")
     ap.add_argument("--launch64", default=None, help="the same for the FP64 stepper (WAVES at most 2)")
+    ap.add_argument("--error-steps", type=int, default=0,
+                    help="step both steppers on to this many steps after the timing before comparing them "
+                         "(error_fp32dev; e.g. 5000, the workload's run length)")
     ap.add_argument("--regularize", action="store_true",
                     help="regularized collision (Eq. ereg) instead of plain BGK; not the headline")
     ap.add_argument("--scheme", type=int, default=2, choices=(1, 2),
@@ -371,6 +391,12 @@ def main():
     # error of the FP32-deviation storage against the FP64 stepper after the same steps
     err = None
     if "f64" in runs:
+        done = args.warmup + args.steps
+        if args.error_steps > done:
+            # both steppers on to the requested step count (after the timing)
+            for r in runs.values():
+                r.step(args.error_steps - done)
+            done = args.error_steps
         r32, x32, y32 = runs["f32"].moments_device()
         r64, x64, y64 = runs["f64"].moments_device()
         umax = torch.sqrt(x64 ** 2 + y64 ** 2).max().clamp_min(1e-300)
@@ -378,7 +404,7 @@ def main():
         drho = ((r32 - r64).abs() / r64.abs())
         err = {"rho_max_rel": float(drho.max()), "rho_rms_rel": float(drho.pow(2).mean().sqrt()),
                "u_max_rel": float(du.max() / umax), "u_rms_rel": float(du.pow(2).mean().sqrt() / umax),
-               "steps": args.warmup + args.steps, "against": "FP64 GPU stepper, same input"}
+               "steps": done, "against": "FP64 GPU stepper, same input"}
         del r32, x32, y32, r64, x64, y64
 
     f32 = results["f32"]

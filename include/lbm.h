@@ -60,6 +60,7 @@ enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 };     /* storage precision               
 enum { LBM_PERIODIC = 0, LBM_SHEAR_WALLS = 1 }; /* boundary in y                 */
 enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_NEAREST = 1 }; /* FP32 storage rounding */
 enum { LBM_PAIR = 0 };  /* waves_per_group of lbm_set_launch: see there          */
+enum { LBM_BATCH_PER_STEP = 0, LBM_BATCH_PERSISTENT = 1 }; /* lbm_batch_set_mode    */
 
 /* Parameters of one run.  Names follow the paper (Sec. II and III). */
 typedef struct {
@@ -272,19 +273,50 @@ lbm_status lbm_batch_step(lbm_batch* batch, int64_t nsteps, int32_t graph_steps,
 lbm_status lbm_batch_set_launch(lbm_batch* batch, int32_t rows_per_wave, void* stream);
 
 /* Time candidate rows-per-item values on the batch itself and keep the
- * fastest: first one value for every run (10 candidates), then, for each
+ * fastest: first one value for every run (10 candidates, in each launch
+ * mode the batch can use: both for FP32 storage, whose mode is then set to
+ * the faster one), then, for each
  * class of runs of one lattice shape and boundary condition (largest total
  * node count first), up to 4 other values for that class alone, kept when
  * they save more than 1%.  The choice for each class is remembered for the
  * process: later lbm_batch_init calls start runs of the same shape,
  * precision, scheme, regularize and boundary from it.  *rows_per_wave
  * receives the common value of the first pass.  The trials advance every
- * run: by (steps_per_trial + 1) steps per candidate.  sync. */
+ * run: by (steps_per_trial + 1) steps per candidate, and persistent-launch
+ * trials by at least 17 (one launch of 16 or more steps).  sync. */
 lbm_status lbm_batch_autotune(lbm_batch* batch, int32_t steps_per_trial, void* stream,
                               int32_t* rows_per_wave);
 
 /* Borrowed handle of run r (valid while the batch lives) for lbm_moments,
  * lbm_get_f, lbm_set_f and lbm_reduce; lbm_step on it is rejected. */
+/* How a batch advances (Sec. III: the paper's runs are independent lattices;
+ * batching them is this library's own scheduling).
+ * LBM_BATCH_PER_STEP (the default): one grouped launch per time step over
+ * the work list.  LBM_BATCH_PERSISTENT (FP32 storage only): one launch runs
+ * up to 64 steps of every run; each work item of step s starts as soon as
+ * the items around it (within the 4-row / 4-column reach of one step) have
+ * finished step s - 1, instead of at a launch boundary, so no run waits for
+ * the slowest item of the step.  Field accesses of that launch are
+ * device-coherent; results are bit-identical to LBM_BATCH_PER_STEP.  Drops a
+ * captured graph.  LBM_EINVAL for an unknown mode or PERSISTENT with FP64
+ * storage.  sync. */
+lbm_status lbm_batch_set_mode(lbm_batch* batch, int32_t mode, void* stream);
+/* The batch's current mode, or -1 for a null batch. */
+int32_t lbm_batch_get_mode(const lbm_batch* batch);
+
+/* Bound, in polls, of each dependency wait of the persistent launch (0 =
+ * the default, about a second).  A wait that exceeds it sets the batch's
+ * error word and lets the launch finish with invalid results, so a launch
+ * never hangs; lbm_batch_sync_status reports it.  Drops a captured graph.
+ * sync. */
+lbm_status lbm_batch_set_wait_limit(lbm_batch* batch, uint32_t polls, void* stream);
+
+/* Wait for `stream`, then report the batch's error word: LBM_EDEVICE (and
+ * the word cleared) if a persistent launch since the last check gave up a
+ * dependency wait, in which case the states of every run are invalid;
+ * LBM_OK otherwise.  sync. */
+lbm_status lbm_batch_sync_status(lbm_batch* batch, void* stream);
+
 lbm_run* lbm_batch_run(lbm_batch* batch, int32_t r);
 
 void lbm_batch_destroy(lbm_batch* batch);

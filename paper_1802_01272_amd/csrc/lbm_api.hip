@@ -241,6 +241,11 @@ struct lbm_run {
     lbm_batch* batch = nullptr;  // non-null for a borrowed batch member
 };
 
+// polls of one dependency wait of the persistent batched launch before it
+// gives up (about a second at ~0.3 us per poll; a correct launch waits at
+// most a few work items' time)
+constexpr uint32_t DEFAULT_WAIT_LIMIT = 1u << 22;
+
 struct lbm_batch {
     int32_t n = 0;
     int precision = 0, scheme = 2, regularize = 0;
@@ -250,6 +255,10 @@ struct lbm_batch {
     BatchItem* d_items = nullptr;
     int32_t nitems = 0;
     int32_t nitems_periodic = 0;  // items [0, nitems_periodic) belong to periodic runs
+    int32_t mode = LBM_BATCH_PER_STEP;
+    int32_t* d_done = nullptr;    // persistent launch: one flag per item
+    uint32_t* d_sync = nullptr;   // persistent launch: [0] ticket, [1] error
+    uint32_t wait_limit = DEFAULT_WAIT_LIMIT;
     int cur = 0;
     int64_t step = 0;
     hipGraph_t graph = nullptr;
@@ -846,6 +855,14 @@ lbm_status lbm_state_device(const lbm_run* run, const void** d_f, int64_t* plane
 
 }  // extern "C"
 
+// most work items a batch can hold (one row per item)
+size_t batch_items_bound(int32_t n, const lbm_params* params)
+{
+    size_t items = 0;
+    for (int i = 0; i < n; ++i) items += (size_t)((params[i].Lx + STRIP - 1) / STRIP) * (size_t)params[i].Ly;
+    return items;
+}
+
 extern "C" size_t lbm_batch_workspace_bytes(int32_t n, const lbm_params* params)
 {
     if (n < 1 || !params) return 0;
@@ -854,14 +871,11 @@ extern "C" size_t lbm_batch_workspace_bytes(int32_t n, const lbm_params* params)
         if (validate(&params[i]) != LBM_OK) return 0;
         total += run_bytes(&params[i]);
     }
-    // tables: runs, coefficient copies, work items
-    size_t items = 0;
-    for (int i = 0; i < n; ++i) {
-        const int64_t ns = (params[i].Lx + STRIP - 1) / STRIP;
-        items += (size_t)ns * (size_t)params[i].Ly;  // upper bound: one row per wavefront
-    }
+    // tables: runs, coefficient copies, work items, and for the persistent
+    // launch one flag per item and the ticket / error words
+    const size_t items = batch_items_bound(n, params);
     total += align_up((size_t)n * sizeof(BatchRun<double>)) + align_up((size_t)n * sizeof(StepCoef<double>))
-           + align_up(items * sizeof(BatchItem));
+           + align_up(items * sizeof(BatchItem)) + align_up(items * sizeof(int32_t)) + ALIGN;
     return total;
 }
 
@@ -898,15 +912,17 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
         br.nstrips = (r.p.Lx + STRIP - 1) / STRIP;
         br.plane = plane_of(&r.p);
         br.walls = r.p.bc_y == LBM_SHEAR_WALLS ? 1 : 0;
-        br.pad_ = 0;
         fill_coef<R>(&r.p, coefs[i]);
         const int nchunks = (r.p.Ly + br.rows - 1) / br.rows;
         std::vector<BatchItem>& dst = br.walls ? wall_items : items;
+        br.item_base = (int32_t)dst.size();  // within its kind; wall runs are offset below
         for (int c = 0; c < nchunks; ++c)
             for (int st = 0; st < br.nstrips; ++st) dst.push_back(BatchItem{i, st, c, 0});
     }
     // periodic items first, then the items of runs with walls
     b->nitems_periodic = (int32_t)items.size();
+    for (auto& br : runs)
+        if (br.walls) br.item_base += b->nitems_periodic;
     items.insert(items.end(), wall_items.begin(), wall_items.end());
     char* p = base;
     b->d_runs = p;
@@ -915,10 +931,51 @@ lbm_status batch_tables(lbm_batch* b, char* base, hipStream_t s)
     p += align_up((size_t)b->n * sizeof(StepCoef<double>));
     b->d_items = reinterpret_cast<BatchItem*>(p);
     b->nitems = (int32_t)items.size();
+    {
+        std::vector<lbm_params> ps(b->n);
+        for (int i = 0; i < b->n; ++i) ps[i] = b->runs[i].p;
+        const size_t bound = batch_items_bound(b->n, ps.data());
+        if (items.size() > bound) return fail(LBM_EINVAL, "batch work list exceeds its bound");
+        p += align_up(bound * sizeof(BatchItem));
+        b->d_done = reinterpret_cast<int32_t*>(p);
+        p += align_up(bound * sizeof(int32_t));
+        b->d_sync = reinterpret_cast<uint32_t*>(p);
+    }
     HIP_TRY(hipMemcpyAsync(b->d_runs, runs.data(), runs.size() * sizeof(BatchRun<R>), hipMemcpyHostToDevice, s), "batch tables");
     HIP_TRY(hipMemcpyAsync(b->d_coefs, coefs.data(), coefs.size() * sizeof(StepCoef<R>), hipMemcpyHostToDevice, s), "batch tables");
     HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s), "batch tables");
     HIP_TRY(hipStreamSynchronize(s), "batch tables");
+    return LBM_OK;
+}
+
+lbm_status batch_launch(lbm_batch* b, hipStream_t s);
+
+// steps in one persistent launch (the item flags count steps of a launch)
+constexpr int32_t PERSIST_MAX_STEPS = 64;
+
+// k steps of every run: k launches of one step, or persistent launches of up
+// to PERSIST_MAX_STEPS steps each
+lbm_status batch_launch_steps(lbm_batch* b, hipStream_t s, int64_t k)
+{
+    if (b->mode != LBM_BATCH_PERSISTENT) {
+        for (int64_t i = 0; i < k; ++i) {
+            lbm_status st = batch_launch(b, s);
+            if (st != LBM_OK) return st;
+        }
+        return LBM_OK;
+    }
+    const int32_t n_per = b->nitems_periodic, n_wall = b->nitems - b->nitems_periodic;
+    const int wmode = n_wall == 0 ? 0 : (n_per == 0 ? 1 : 2);
+    while (k > 0) {
+        const int32_t m = (int32_t)std::min<int64_t>(k, PERSIST_MAX_STEPS);
+        const hipError_t e = launch_batch_persistent<float>(
+            static_cast<const BatchRun<float>*>(b->d_runs), b->n, static_cast<const StepCoef<float>*>(b->d_coefs),
+            b->d_items, b->nitems, b->cur, m, b->scheme, b->regularize, wmode, b->d_sync, b->d_done, b->d_sync + 1,
+            b->wait_limit, s);
+        if (e != hipSuccess) return hip_fail(e, "persistent batch launch");
+        b->cur ^= (m & 1);
+        k -= m;
+    }
     return LBM_OK;
 }
 
@@ -1002,6 +1059,7 @@ lbm_status lbm_batch_init(int32_t n, const lbm_params* params, void* d_ws, size_
         p += run_bytes(&params[i]);
     }
     lbm_status st = (b->precision == LBM_FP32_DEV) ? batch_tables<float>(b, p, s) : batch_tables<double>(b, p, s);
+    if (st == LBM_OK && hipMemset(b->d_sync, 0, ALIGN) != hipSuccess) st = fail(LBM_EDEVICE, "batch init: sync words");
     if (st != LBM_OK) {
         delete b;
         return st;
@@ -1028,7 +1086,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int32_t graph_steps, voi
         }
         while (nsteps - done >= gsteps) {
             if (b->cur != 0) {
-                lbm_status st = batch_launch(b, s);
+                lbm_status st = batch_launch_steps(b, s, 1);
                 if (st != LBM_OK) return st;
                 batch_advance_members(b, 1);
                 ++done;
@@ -1038,15 +1096,13 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int32_t graph_steps, voi
                 if (!b->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking), "capture stream");
                 HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
                 const int saved = b->cur;
-                for (int32_t i = 0; i < gsteps; ++i) {
-                    lbm_status st = batch_launch(b, b->capture_stream);
-                    if (st != LBM_OK) {
-                        hipGraph_t g;
-                        (void)hipStreamEndCapture(b->capture_stream, &g);
-                        if (g) (void)hipGraphDestroy(g);
-                        b->cur = saved;
-                        return st;
-                    }
+                lbm_status st = batch_launch_steps(b, b->capture_stream, gsteps);
+                if (st != LBM_OK) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(b->capture_stream, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    b->cur = saved;
+                    return st;
                 }
                 b->cur = saved;
                 HIP_TRY(hipStreamEndCapture(b->capture_stream, &b->graph), "end capture");
@@ -1059,10 +1115,48 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int32_t graph_steps, voi
             done += gsteps;
         }
     }
-    for (; done < nsteps; ++done) {
-        lbm_status st = batch_launch(b, s);
+    if (done < nsteps) {
+        lbm_status st = batch_launch_steps(b, s, nsteps - done);
         if (st != LBM_OK) return st;
-        batch_advance_members(b, 1);
+        batch_advance_members(b, nsteps - done);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_mode(lbm_batch* b, int32_t mode, void* stream)
+{
+    if (!b) return fail(LBM_EINVAL, "null batch");
+    if (mode != LBM_BATCH_PER_STEP && mode != LBM_BATCH_PERSISTENT) return fail(LBM_EINVAL, "unknown batch mode");
+    if (mode == LBM_BATCH_PERSISTENT && b->precision != LBM_FP32_DEV)
+        return fail(LBM_EINVAL, "the persistent batched launch needs FP32 storage");
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "batch set mode");
+    b->mode = mode;
+    drop_graph(b);
+    return LBM_OK;
+}
+
+int32_t lbm_batch_get_mode(const lbm_batch* b) { return b ? b->mode : -1; }
+
+lbm_status lbm_batch_set_wait_limit(lbm_batch* b, uint32_t polls, void* stream)
+{
+    if (!b) return fail(LBM_EINVAL, "null batch");
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "batch wait limit");
+    b->wait_limit = polls ? polls : DEFAULT_WAIT_LIMIT;
+    drop_graph(b);
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_sync_status(lbm_batch* b, void* stream)
+{
+    if (!b) return fail(LBM_EINVAL, "null batch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamSynchronize(s), "batch status");
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, b->d_sync + 1, sizeof(err), hipMemcpyDeviceToHost), "batch status");
+    if (err) {
+        HIP_TRY(hipMemset(b->d_sync + 1, 0, sizeof(uint32_t)), "batch status");
+        return fail(LBM_EDEVICE, "a dependency wait of the persistent batched launch exceeded its bound; "
+                                 "the states advanced since the last check are invalid");
     }
     return LBM_OK;
 }
@@ -1096,20 +1190,25 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps_per_trial, void* strea
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "batch autotune");
     HIP_TRY(hipEventCreate(&e1), "batch autotune");
-    // device time of steps_per_trial steps with the batch's current work list
-    // (one untimed step first)
+    // device time per step of a trial with the batch's current work list and
+    // mode (one untimed step first): steps_per_trial steps, or in one
+    // persistent launch at least PERSIST_TRIAL_STEPS, since that launch's
+    // start and end are shared by all its steps
+    constexpr int32_t PERSIST_TRIAL_STEPS = 16;
     auto trial = [&](double* ms_out) -> lbm_status {
+        const int32_t k = b->mode == LBM_BATCH_PERSISTENT ? std::max(steps_per_trial, PERSIST_TRIAL_STEPS)
+                                                          : steps_per_trial;
         lbm_status st = lbm_batch_step(b, 1, 0, stream);
         if (st != LBM_OK) return st;
         if (hipEventRecord(e0, s) != hipSuccess) return fail(LBM_EDEVICE, "batch autotune event");
-        st = lbm_batch_step(b, steps_per_trial, 0, stream);
+        st = lbm_batch_step(b, k, 0, stream);
         if (st != LBM_OK) return st;
         float ms = 0;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess
             || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
             return fail(LBM_EDEVICE, "batch autotune timing");
-        *ms_out = ms;
-        return LBM_OK;
+        *ms_out = ms / k;
+        return lbm_batch_sync_status(b, stream);
     };
     // rebuild the work list with the rows now set on each member
     auto retable = [&]() -> lbm_status {
@@ -1119,20 +1218,31 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps_per_trial, void* strea
         return (b->precision == LBM_FP32_DEV) ? batch_tables<float>(b, base, s) : batch_tables<double>(b, base, s);
     };
     lbm_status st = LBM_OK;
-    // 1. one rows value for every run
+    // 1. one rows value for every run, in each launch mode the batch can use
+    // (FP32: one launch per step, or the persistent launch); the fastest
+    // pair of mode and rows is kept
     const int rows_c[] = {16, 24, 32, 40, 48, 64, 96, 128, 192, 256};
     double best = 1e300;
     int best_rows = rows_c[0];
-    for (int rows : rows_c) {
-        double ms = 0;
-        st = lbm_batch_set_launch(b, rows, stream);
-        if (st == LBM_OK) st = trial(&ms);
-        if (st != LBM_OK) break;
-        if (ms < best) {
-            best = ms;
-            best_rows = rows;
+    int best_mode = LBM_BATCH_PER_STEP;
+    const int modes[2] = {LBM_BATCH_PER_STEP, LBM_BATCH_PERSISTENT};
+    const int nmodes = b->precision == LBM_FP32_DEV ? 2 : 1;
+    for (int mi = 0; mi < nmodes && st == LBM_OK; ++mi) {
+        st = lbm_batch_set_mode(b, modes[mi], stream);
+        for (int rows : rows_c) {
+            if (st != LBM_OK) break;
+            double ms = 0;
+            st = lbm_batch_set_launch(b, rows, stream);
+            if (st == LBM_OK) st = trial(&ms);
+            if (st != LBM_OK) break;
+            if (ms < best) {
+                best = ms;
+                best_rows = rows;
+                best_mode = modes[mi];
+            }
         }
     }
+    if (st == LBM_OK) st = lbm_batch_set_mode(b, best_mode, stream);
     if (st == LBM_OK) st = lbm_batch_set_launch(b, best_rows, stream);
     // 2. then each class of runs (lattice shape and boundary), largest total
     // node count first, tries other rows values with the rest fixed and keeps

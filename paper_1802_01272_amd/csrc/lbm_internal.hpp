@@ -114,7 +114,8 @@ struct BatchRun {
     int32_t rows, nstrips;
     int64_t plane;
     int32_t walls;      // shear walls (1) or periodic in y (0)
-    int32_t pad_;
+    int32_t item_base;  // index of the run's first work item; its items
+                        // follow chunk by chunk, strip by strip
 };
 
 // Launch shape of the step kernel.
@@ -133,6 +134,17 @@ template <typename R>
 hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coefs,
                              const BatchItem* d_items, int32_t nitems, int32_t cur, int scheme,
                              int regularize, int wmode, int waves_per_group, hipStream_t s);
+// Persistent batched launch (FP32 storage only): nsteps steps of every run
+// from parity cur0 in one launch of at most max_groups workgroups, after a
+// reset of *ticket and done[0..nitems); *err is set (and left set) when a
+// dependency wait exceeds wait_limit polls.  The runs' step counters are
+// moved on by a second kernel.
+template <typename R>
+hipError_t launch_batch_persistent(const BatchRun<R>* d_runs, int32_t nruns, const StepCoef<R>* d_coefs,
+                                   const BatchItem* d_items, int32_t nitems, int32_t cur0, int32_t nsteps,
+                                   int scheme, int regularize, int wmode, uint32_t* ticket, int32_t* done,
+                                   uint32_t* err, uint32_t wait_limit, hipStream_t s);
+
 template <typename R>
 hipError_t launch_init(R* f, const StepCoef<R>* coef, const double* rho, const double* ux,
                        const double* uy, int64_t n, int64_t plane, hipStream_t s);

@@ -111,22 +111,32 @@ __device__ __forceinline__ FieldRsrc make_field_rsrc(const R* base, int64_t plan
     f.half[1] = __builtin_amdgcn_make_buffer_rsrc((void*)(base + 8 * plane), (short)0, -1, 0x00020000);
     return f;
 }
+// CPOL: cache policy of the access.  0 = default; CPOL_DEVICE = device
+// scope (SC1): loads see stores of other XCDs that have completed, stores
+// complete at the device's point of coherence (the persistent batched launch,
+// where a workgroup reads what workgroups on other XCDs wrote in the same
+// launch).
+constexpr int CPOL_DEVICE = 16;
+template <int CPOL = 0>
 __device__ __forceinline__ void buf_load(float& v, const FieldRsrc& f, int k, uint32_t voff, uint32_t pbytes)
 {
-    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0));
+    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, CPOL));
 }
+template <int CPOL = 0>
 __device__ __forceinline__ void buf_load(double& v, const FieldRsrc& f, int k, uint32_t voff, uint32_t pbytes)
 {
-    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0));
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, CPOL));
 }
+template <int CPOL = 0>
 __device__ __forceinline__ void buf_store(float v, const FieldRsrc& f, int k, uint32_t voff, uint32_t pbytes)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, CPOL);
 }
+template <int CPOL = 0>
 __device__ __forceinline__ void buf_store(double v, const FieldRsrc& f, int k, uint32_t voff, uint32_t pbytes)
 {
     using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(f.half[0], 0u, 0u, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), f.half[k >> 3], voff, (uint32_t)(k & 7) * pbytes, CPOL);
 }
 
 // 1/x for x of order one (densities, 1 - b rho): hardware reciprocal refined
@@ -233,7 +243,7 @@ template <typename R> struct G5W {
 // and the colliding wavefront of a pair that shares the LDS ring of advected
 // rows (pend) and a ring of their densities (dsl); one barrier per row, the
 // collider one row behind the advector.
-template <typename R, int SCHEME, bool REG, bool WALLS, int ROLE = 0>
+template <typename R, int SCHEME, bool REG, bool WALLS, int ROLE = 0, int CPOL = 0>
 __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restrict__ fout,
                                            const StepCoef<R>* __restrict__ C,
                                            const int Lx, const int Ly, const int64_t plane,
@@ -322,7 +332,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
     if constexpr (ADV) {
         const uint32_t voff = row_voff(y0 - 4);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) buf_load(B[0][k], src, k, voff, pbytes);
+        for (int k = 0; k < 16; ++k) buf_load<CPOL>(B[0][k], src, k, voff, pbytes);
     }
 
     // COLL = false: the first eight rows of the march only fill the rings
@@ -360,7 +370,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         if constexpr (ADV && !WORK) {
             const uint32_t nvoff = row_voff(r + 1);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) buf_load(fm1[k], src, k, nvoff, pbytes);
+            for (int k = 0; k < 16; ++k) buf_load<CPOL>(fm1[k], src, k, nvoff, pbytes);
             // the D2 carry of the first advecting row (the rows it reads are
             // loaded by the last of these rows)
             if constexpr (CARRY_D2) {
@@ -379,7 +389,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
         {
             const uint32_t nvoff = row_voff(r + 1);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) buf_load(fm1[k], src, k, nvoff, pbytes);
+            for (int k = 0; k < 16; ++k) buf_load<CPOL>(fm1[k], src, k, nvoff, pbytes);
         }
 
         // --- first step of the split: advection of row a -----------------------
@@ -702,7 +712,7 @@ __device__ __forceinline__ void strip_step(const R* __restrict__ fin, R* __restr
                     R fnew;
                     if constexpr (sizeof(R) == 4) fnew = store_round(xn[sv], xn[sv ^ 1], seed, srm);
                     else fnew = (R)xn[sv];
-                    if (store_row && out_lane) buf_store(fnew, dst, K, soff, pbytes);
+                    if (store_row && out_lane) buf_store<CPOL>(fnew, dst, K, soff, pbytes);
                 }
             });
         }
@@ -882,6 +892,150 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void b
                                               run.plane, it.strip, y0, y1, pend, seed, dsl);
         }
     });
+}
+
+// ----------------------------------------------------------------------------
+// Persistent batched launch (FP32 storage, a pair of wavefronts per work
+// item): one launch advances every run of the batch by nsteps, with no
+// launch boundary between steps.  Workgroups take tickets t = s * nitems + i
+// in order from one counter (item i of step s).  Before item i of step s
+// reads its input, its advecting wavefront waits until every item whose
+// output rows and columns overlap the item's input (its run's items within
+// 4 rows and 4 columns, periodic wrap included) has finished step s - 1:
+// that covers the reads of step s (the neighbours' outputs of step s - 1)
+// and the writes of step s (the buffer that the neighbours read in step
+// s - 1; the neighbourhood is symmetric).  A ticket only waits for smaller
+// tickets, which running workgroups hold, so the launch always drains.
+// Field accesses are device-coherent (CPOL_DEVICE), and the colliding
+// wavefront publishes done[i] = s + 1 only after its stores have completed.
+// Every wait is bounded: past wait_limit polls the launch sets *err, stops
+// waiting and finishes (its results are then invalid).  The step counters
+// of the stochastic rounding are read, not written; batch_seq_kernel moves
+// them on after the launch.
+
+// first index and count of the blocks of `per` (the last one ragged) of
+// 0..L-1 that cover positions lo..hi, wrapped periodically or clipped
+__device__ __forceinline__ void block_span(int lo, int hi, int L, int per, int nblk, bool wrap, int& first,
+                                           int& count)
+{
+    if (!wrap) {
+        lo = max(lo, 0);
+        hi = min(hi, L - 1);
+        first = lo / per;
+        count = hi / per - first + 1;
+        return;
+    }
+    if (hi - lo + 1 >= L) {
+        first = 0;
+        count = nblk;
+        return;
+    }
+    lo = ((lo % L) + L) % L;
+    hi = ((hi % L) + L) % L;
+    first = lo / per;
+    const int last = hi / per;
+    // a range that wraps past L - 1 runs from block `first` to the end and
+    // on from block 0 to `last`
+    count = lo > hi ? min(last + nblk - first + 1, nblk) : last - first + 1;
+}
+
+__device__ __forceinline__ bool wait_done(const int32_t* done, int j, int s, uint32_t limit, uint32_t* err)
+{
+    uint32_t polls = 0;
+    while (__hip_atomic_load(done + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < s) {
+        if (++polls > limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+template <typename R, int SCHEME, bool REG, int WMODE>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void batch_persistent_kernel(
+    const BatchRun<R>* __restrict__ runs, const StepCoef<R>* __restrict__ coefs, const BatchItem* __restrict__ items,
+    int nitems, int cur0, int nsteps, uint32_t* __restrict__ ticket, int32_t* __restrict__ done,
+    uint32_t* __restrict__ err, uint32_t wait_limit)
+{
+    __shared__ uint32_t tick;
+    const int role = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint32_t total = (uint32_t)nitems * (uint32_t)nsteps;
+    double* const pend = reinterpret_cast<double*>(step_lds);  // PAIR_STEP_LDS bytes
+    double* const dsl = pend + PENDING_ROWS * 16 * WAVE;
+    for (;;) {
+        if (threadIdx.x == 0) tick = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t t = __builtin_amdgcn_readfirstlane(tick);
+        __syncthreads();  // tick is read by both wavefronts before it is written again
+        if (t >= total) break;
+        const int s = (int)(t / (uint32_t)nitems);
+        const int i = (int)(t - (uint32_t)s * (uint32_t)nitems);
+        const BatchItem it = items[i];
+        const BatchRun<R> run = runs[it.run];
+        const int y0 = it.chunk * run.rows;
+        const int y1 = min(y0 + run.rows, run.Ly);
+        const int cur = (cur0 + s) & 1;
+        R* const fa = run.f[0];
+        R* const fb = run.f[1];
+        if (role == 0 && s > 0 && lane == 0) {
+            const int x0 = it.strip * STRIP;
+            const int x1 = min(x0 + STRIP, run.Lx);
+            const int nchunks = (run.Ly + run.rows - 1) / run.rows;
+            int cf, cn, sf, sn;
+            block_span(y0 - 4, y1 + 3, run.Ly, run.rows, nchunks, run.walls == 0, cf, cn);
+            block_span(x0 - HALO, x1 - 1 + HALO, run.Lx, STRIP, run.nstrips, true, sf, sn);
+            bool ok = true;
+            for (int a = 0; a < cn && ok; ++a) {
+                const int c = (cf + a) % nchunks;
+                for (int b = 0; b < sn && ok; ++b)
+                    ok = wait_done(done, run.item_base + c * run.nstrips + (sf + b) % run.nstrips, s, wait_limit, err);
+            }
+        }
+        // the field loads below are not moved above the wait
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        with_walls<WMODE>(run.walls, [&](auto wl) {
+            constexpr bool WL = decltype(wl)::value;
+            if (role == 0) {
+                strip_step<R, SCHEME, REG, WL, 1, CPOL_DEVICE>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx,
+                                                               run.Ly, run.plane, it.strip, y0, y1, pend, 0u, dsl);
+            } else {
+                const uint32_t n0 = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(run.seq + cur0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                const uint32_t seed = mix32(n0 + (uint32_t)s);
+                strip_step<R, SCHEME, REG, WL, 2, CPOL_DEVICE>(cur ? fb : fa, cur ? fa : fb, coefs + it.run, run.Lx,
+                                                               run.Ly, run.plane, it.strip, y0, y1, pend, seed, dsl);
+            }
+        });
+        if (role == 1) {
+            // this wavefront's stores have completed before the item is published
+            __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (lane == 0) __hip_atomic_store(done + i, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Clear the persistent launch's ticket counter and item flags.
+__global__ void batch_reset_kernel(uint32_t* __restrict__ ticket, int32_t* __restrict__ done, int nitems)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nitems) done[i] = 0;
+    if (i == 0) *ticket = 0u;
+}
+
+// After a persistent launch of nsteps steps from parity cur0: leave each
+// run's step counter pair as nsteps launches of one step would
+// (seq[(cur0 + nsteps) & 1] = n0 + nsteps, the other slot one less).
+template <typename R>
+__global__ void batch_seq_kernel(const BatchRun<R>* __restrict__ runs, int nruns, int cur0, int nsteps)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nruns) return;
+    uint32_t* seq = runs[r].seq;
+    const uint32_t n0 = seq[cur0];
+    seq[(cur0 + nsteps) & 1] = n0 + (uint32_t)nsteps;
+    seq[(cur0 + nsteps + 1) & 1] = n0 + (uint32_t)nsteps - 1u;
 }
 
 // ----------------------------------------------------------------------------
@@ -1152,6 +1306,71 @@ hipError_t launch_batch_step(const BatchRun<R>* d_runs, const StepCoef<R>* d_coe
     return hipGetLastError();
 }
 
+// workgroups of one persistent kernel that the device holds at once
+template <typename K>
+int resident_groups(K kernel, int block, size_t lds)
+{
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+template <typename R>
+hipError_t launch_batch_persistent(const BatchRun<R>* d_runs, int32_t nruns, const StepCoef<R>* d_coefs,
+                                   const BatchItem* d_items, int32_t nitems, int32_t cur0, int32_t nsteps,
+                                   int scheme, int regularize, int wmode, uint32_t* ticket, int32_t* done,
+                                   uint32_t* err, uint32_t wait_limit, hipStream_t s)
+{
+    if constexpr (sizeof(R) != 4) {
+        return hipErrorInvalidValue;
+    } else {
+        if (nitems <= 0 || nsteps <= 0) return hipSuccess;
+        if (wmode < 0 || wmode > 2 || (int64_t)nitems * nsteps >= (int64_t)1 << 31) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(batch_reset_kernel, dim3(grid_for(nitems, 256)), dim3(256), 0, s, ticket, done, nitems);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t total = (int64_t)nitems * nsteps;
+#define LBM_PERSIST_LAUNCH(SC, RG, WM)                                                                    \
+    {                                                                                                     \
+        auto* k = batch_persistent_kernel<R, SC, RG, WM>;                                                 \
+        const int cap = resident_groups(k, 2 * WAVE, PAIR_STEP_LDS);                                      \
+        if (cap <= 0) return hipErrorInvalidConfiguration;                                                \
+        const int grid = (int)std::min<int64_t>(cap, total);                                              \
+        hipLaunchKernelGGL(k, dim3(grid), dim3(2 * WAVE), PAIR_STEP_LDS, s, d_runs, d_coefs, d_items, nitems, \
+                           cur0, nsteps, ticket, done, err, wait_limit);                                  \
+    }
+        if (scheme == 1) {
+            if (regularize) {
+                if (wmode == 0) LBM_PERSIST_LAUNCH(1, true, 0)
+                else if (wmode == 1) LBM_PERSIST_LAUNCH(1, true, 1)
+                else LBM_PERSIST_LAUNCH(1, true, 2)
+            } else {
+                if (wmode == 0) LBM_PERSIST_LAUNCH(1, false, 0)
+                else if (wmode == 1) LBM_PERSIST_LAUNCH(1, false, 1)
+                else LBM_PERSIST_LAUNCH(1, false, 2)
+            }
+        } else {
+            if (regularize) {
+                if (wmode == 0) LBM_PERSIST_LAUNCH(2, true, 0)
+                else if (wmode == 1) LBM_PERSIST_LAUNCH(2, true, 1)
+                else LBM_PERSIST_LAUNCH(2, true, 2)
+            } else {
+                if (wmode == 0) LBM_PERSIST_LAUNCH(2, false, 0)
+                else if (wmode == 1) LBM_PERSIST_LAUNCH(2, false, 1)
+                else LBM_PERSIST_LAUNCH(2, false, 2)
+            }
+        }
+#undef LBM_PERSIST_LAUNCH
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((batch_seq_kernel<R>), dim3(grid_for(nruns, 64)), dim3(64), 0, s, d_runs, nruns, cur0,
+                           nsteps);
+        return hipGetLastError();
+    }
+}
+
 template <typename R>
 hipError_t launch_init(R* f, const StepCoef<R>* coef, const double* rho, const double* ux, const double* uy,
                        int64_t n, int64_t plane, hipStream_t s)
@@ -1219,7 +1438,10 @@ hipError_t launch_reduce(const R* f, const StepCoef<R>* coef, int32_t Lx, int32_
     template hipError_t launch_set_plane<R>(R*, const StepCoef<R>*, int, const double*, int64_t, int64_t,    \
                                             hipStream_t);                                                    \
     template hipError_t launch_reduce<R>(const R*, const StepCoef<R>*, int32_t, int32_t, int64_t, double,    \
-                                         double*, int32_t, double*, hipStream_t);
+                                         double*, int32_t, double*, hipStream_t);                            \
+    template hipError_t launch_batch_persistent<R>(const BatchRun<R>*, int32_t, const StepCoef<R>*,          \
+                                                   const BatchItem*, int32_t, int32_t, int32_t, int, int, int, \
+                                                   uint32_t*, int32_t*, uint32_t*, uint32_t, hipStream_t);
 LBM_INSTANTIATE(float)
 LBM_INSTANTIATE(double)
 #undef LBM_INSTANTIATE

@@ -22,6 +22,7 @@ FP64, FP32_DEV = 0, 1
 PERIODIC, SHEAR_WALLS = 0, 1
 ROUND_STOCHASTIC, ROUND_NEAREST = 0, 1
 PAIR = 0  # waves_per_group of a launch shape: two wavefronts per strip (FP32 storage)
+BATCH_PER_STEP, BATCH_PERSISTENT = 0, 1  # lbm_batch_set_mode
 
 
 class LbmError(RuntimeError):
@@ -136,6 +137,10 @@ def _load():
         "lbm_batch_set_launch": ([vp, ctypes.c_int32, vp], st),
         "lbm_batch_autotune": ([vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)], st),
         "lbm_batch_run": ([vp, ctypes.c_int32], vp),
+        "lbm_batch_set_mode": ([vp, ctypes.c_int32, vp], st),
+        "lbm_batch_get_mode": ([vp], ctypes.c_int32),
+        "lbm_batch_set_wait_limit": ([vp, ctypes.c_uint32, vp], st),
+        "lbm_batch_sync_status": ([vp, vp], st),
         "lbm_batch_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
@@ -385,11 +390,29 @@ class Batch:
     def set_launch(self, rows_per_wave: int, stream=None):
         _check(LIB.lbm_batch_set_launch(self.handle, int(rows_per_wave), _stream_handle(self.torch, stream)))
 
+    def set_mode(self, mode: int, stream=None):
+        """BATCH_PER_STEP (one launch per step) or BATCH_PERSISTENT (FP32:
+        one launch for many steps, items start when their neighbours finish)."""
+        _check(LIB.lbm_batch_set_mode(self.handle, int(mode), _stream_handle(self.torch, stream)))
+
+    @property
+    def mode(self) -> int:
+        return int(LIB.lbm_batch_get_mode(self.handle))
+
+    def set_wait_limit(self, polls: int, stream=None):
+        _check(LIB.lbm_batch_set_wait_limit(self.handle, int(polls), _stream_handle(self.torch, stream)))
+
+    def sync_status(self, stream=None):
+        """Raise LbmError if a persistent launch gave up a dependency wait."""
+        _check(LIB.lbm_batch_sync_status(self.handle, _stream_handle(self.torch, stream)))
+
     def autotune(self, steps_per_trial: int = 3, stream=None) -> int:
-        """Pick the rows per work item on the batch itself, one common value
-        and then one per class of runs of a shape and boundary (remembered for
-        later batches); advances every run by (steps_per_trial + 1) steps per
-        trial, 10 to 11 + 4 * classes trials.  Returns the common value."""
+        """Pick the launch mode and the rows per work item on the batch itself,
+        one common value and then one per class of runs of a shape and
+        boundary (remembered for later batches); advances every run by
+        (steps_per_trial + 1) steps per trial (at least 17 for a trial of the
+        persistent launch), 10 (FP64) or 20 (FP32) common trials plus up to
+        1 + 4 per class.  Returns the common value."""
         rows = ctypes.c_int32()
         _check(LIB.lbm_batch_autotune(self.handle, int(steps_per_trial), _stream_handle(self.torch, stream),
                                       ctypes.byref(rows)))

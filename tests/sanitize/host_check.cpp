@@ -191,6 +191,10 @@ int main()
         CHECK(lbm_batch_set_launch(nullptr, 32, nullptr) != LBM_OK, "launch of a null batch");
         CHECK(lbm_batch_autotune(nullptr, 1, nullptr, &r) != LBM_OK, "autotune of a null batch");
         CHECK(lbm_batch_run(nullptr, 0) == nullptr, "member of a null batch");
+        CHECK(lbm_batch_set_mode(nullptr, LBM_BATCH_PERSISTENT, nullptr) != LBM_OK, "mode of a null batch");
+        CHECK(lbm_batch_get_mode(nullptr) == -1, "mode query of a null batch");
+        CHECK(lbm_batch_set_wait_limit(nullptr, 1, nullptr) != LBM_OK, "wait limit of a null batch");
+        CHECK(lbm_batch_sync_status(nullptr, nullptr) != LBM_OK, "status of a null batch");
         lbm_batch_destroy(nullptr);
     }
 

@@ -37,10 +37,14 @@ def make_params(Lx, Ly, scheme=2, reg=0, bc=0, precision=0, **kw):
     return p
 
 
-def gpu_step_from(p, f, nsteps=1, launch=None):
+def gpu_step_from(p, f, nsteps=1, launch=None, start_step=0):
+    """f advanced by nsteps single-run steps, starting at step count
+    start_step (FP32 storage: the stochastic rounding follows the step
+    count)."""
     run = lbm.Run(p, 1.0, 0.0, 0.0)
     if launch:
         run.set_launch(*launch)
+    run.step(start_step)
     run.set_f(f)
     run.step(nsteps)
     out = run.get_f()
@@ -424,11 +428,13 @@ def test_batch_equals_single_runs(graph_steps, precision):
         assert np.array_equal(m.get_f(), ref)
 
 
-def test_batch_set_launch_and_autotune():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_set_launch_and_autotune(precision):
     """A batch re-chunked to another rows-per-wavefront still equals single
-    runs with that launch shape; the autotuner keeps one of its candidates and
-    its trial steps advance every member."""
-    specs = [make_params(70, 50, bc=1), make_params(33, 19)]
+    runs with that launch shape; the autotuner keeps one of its candidates
+    (and, for FP32, one of the two launch modes) and its trial steps advance
+    every member."""
+    specs = [make_params(70, 50, bc=1, precision=precision), make_params(33, 19, precision=precision)]
     states = [random_state(p, 95 + i) for i, p in enumerate(specs)]
     singles = [gpu_step_from(p, f, nsteps=3, launch=(5, 1)) for p, f in zip(specs, states)]
     batch = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
@@ -440,19 +446,26 @@ def test_batch_set_launch_and_autotune():
         assert np.array_equal(m.get_f(), ref)
     rows = batch.autotune(1)
     assert rows in (16, 24, 32, 40, 48, 64, 96, 128, 192, 256)
-    # 10 common candidates, one re-timing, up to 4 per class (two classes)
+    # 10 common candidates per launch mode (one mode for FP64, two for
+    # FP32, persistent trials of 1 + 16 steps), one re-timing, up to 4 per
+    # class (two classes) in the chosen mode
+    common = 10 * 2 + (0 if precision == 0 else 10 * 17)
+    per = 17 if batch.mode == lbm.BATCH_PERSISTENT else 2
     counts = {m.step_count for m in batch.runs}
-    assert len(counts) == 1 and 3 + 2 * 11 <= counts.pop() <= 3 + 2 * 19
+    assert len(counts) == 1 and 3 + common + per <= counts.pop() <= 3 + common + 9 * per
+    assert batch.mode in ((lbm.BATCH_PER_STEP,) if precision == 0 else (lbm.BATCH_PER_STEP, lbm.BATCH_PERSISTENT))
     per_run = [m.get_launch()[0] for m in batch.runs]
     assert all(r in (rows, rows // 2, (3 * rows) // 4, (3 * rows) // 2, 2 * rows) for r in per_run)
     st = batch.runs[0].reduce(1.0)
     assert st["n_nonfinite"] == 0
     # the per-class choice stays bit-exact against single runs with that shape
     states = [random_state(p, 97 + i) for i, p in enumerate(specs)]
-    singles = [gpu_step_from(p, f, nsteps=3, launch=(r, 1)) for p, f, r in zip(specs, states, per_run)]
+    at = batch.runs[0].step_count
+    singles = [gpu_step_from(p, f, nsteps=3, launch=(r, 1), start_step=at) for p, f, r in zip(specs, states, per_run)]
     for m, f in zip(batch.runs, states):
         m.set_f(f)
     batch.step(3, graph_steps=3)
+    batch.sync_status()
     for m, ref in zip(batch.runs, singles):
         assert np.array_equal(m.get_f(), ref)
     batch.close()
@@ -460,6 +473,89 @@ def test_batch_set_launch_and_autotune():
     again = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
     assert [m.get_launch()[0] for m in again.runs] == per_run
     again.close()
+
+
+PERSIST_SPECS = {
+    # (Lx, Ly, walls): ragged strips and chunks, a single-item lattice, and
+    # lattices whose last chunk is shorter than the 4-row reach of a step
+    "mixed": [(70, 50, 1), (33, 19, 0), (128, 64, 1), (9, 7, 0), (57, 130, 0), (200, 66, 1)],
+    "periodic": [(33, 19, 0), (9, 7, 0), (57, 130, 0), (120, 121, 0)],
+    "walls": [(70, 50, 1), (128, 64, 1), (40, 9, 1)],
+}
+
+
+@pytest.mark.parametrize("rows", [5, 64])
+@pytest.mark.parametrize("graph_steps", [0, 6])
+@pytest.mark.parametrize("kinds", sorted(PERSIST_SPECS))
+def test_persistent_batch_equals_single_runs(kinds, graph_steps, rows):
+    """The persistent batched launch (FP32: one launch for up to 64 steps,
+    each work item waiting only for its neighbours of the previous step)
+    equals single runs bitwise over 150 steps: periodic and wall runs in one
+    launch, rows per item down to 5 (chunks of 2 rows at the lattice edge),
+    several launches (the 64-step bound crossed at odd parity), and launches
+    replayed from a captured graph."""
+    specs = [make_params(Lx, Ly, bc=bc, precision=1) for Lx, Ly, bc in PERSIST_SPECS[kinds]]
+    states = [random_state(p, 300 + i) for i, p in enumerate(specs)]
+    singles = [gpu_step_from(p, f, nsteps=150) for p, f in zip(specs, states)]
+    batch = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
+    batch.set_launch(rows)
+    batch.set_mode(lbm.BATCH_PERSISTENT)
+    assert batch.mode == lbm.BATCH_PERSISTENT
+    for m, f in zip(batch.runs, states):
+        m.set_f(f)
+    batch.step(71, graph_steps=graph_steps)
+    batch.step(79, graph_steps=graph_steps)
+    batch.sync_status()
+    for m, ref in zip(batch.runs, singles):
+        assert m.step_count == 150
+        got = m.get_f()
+        assert np.all(np.isfinite(ref))
+        assert np.array_equal(got, ref)
+    # switching back continues the same trajectory
+    more = [gpu_step_from(p, ref, nsteps=3, start_step=150) for p, ref in zip(specs, singles)]
+    for m, ref in zip(batch.runs, singles):
+        m.set_f(ref)
+    batch.set_mode(lbm.BATCH_PER_STEP)
+    batch.step(3)
+    for m, ref in zip(batch.runs, more):
+        assert np.array_equal(m.get_f(), ref)
+    batch.close()
+
+
+def test_persistent_batch_reports_a_wait_past_its_bound():
+    """A dependency wait that exceeds its bound ends the launch with an
+    error instead of hanging: with a bound of one poll, the item of step 1
+    of a one-item batch gives up while step 0 still runs, and the status
+    call reports it; the default bound then gives exact results again."""
+    p = make_params(40, 40, precision=1)
+    f = random_state(p, 321)
+    batch = lbm.Batch([p], [(1.0, 0.0, 0.0)])
+    batch.set_launch(64)
+    batch.set_mode(lbm.BATCH_PERSISTENT)
+    batch.set_wait_limit(1)
+    batch.runs[0].set_f(f)
+    batch.step(8)
+    with pytest.raises(lbm.LbmError) as ei:
+        batch.sync_status()
+    assert ei.value.status == lbm.LBM_EDEVICE
+    batch.sync_status()  # the error word was cleared
+    batch.set_wait_limit(0)
+    batch.runs[0].set_f(f)
+    batch.step(8)
+    batch.sync_status()
+    assert np.array_equal(batch.runs[0].get_f(), gpu_step_from(p, f, nsteps=8, start_step=8))
+    batch.close()
+
+
+def test_persistent_mode_needs_fp32():
+    batch = lbm.Batch([make_params(33, 19, precision=0)], [(1.0, 0.0, 0.0)])
+    with pytest.raises(lbm.LbmError) as ei:
+        batch.set_mode(lbm.BATCH_PERSISTENT)
+    assert ei.value.status == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError):
+        batch.set_mode(7)
+    assert batch.mode == lbm.BATCH_PER_STEP
+    batch.close()
 
 
 def test_rejects_bad_parameters():
