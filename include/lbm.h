@@ -162,7 +162,17 @@ lbm_status lbm_init_device(const lbm_params* p, void* d_ws, size_t ws_bytes, voi
 lbm_status lbm_attach(const lbm_params* p, void* d_ws, size_t ws_bytes, int64_t step,
                       lbm_run** out);
 
-/* Advance nsteps >= 0 time steps.  async. */
+/* Advance nsteps >= 0 time steps of the split scheme of Sec. II C: each
+ * step advects every f_k with CTU1 (Eq. ctueq) or CTU2 (Sec. II C 2, MC
+ * limiter), optionally regularizes the advected state (Eq. ereg), then
+ * applies the BGK collision toward f^eq (Eq. herfeq) and the force term
+ * (Eq. herforce) with g from Eqs. (eder)/(evdw) on the advected density;
+ * with shear walls the ghost rows keep f^eq(rho_wall, -+u_wall) (Sec. III C),
+ * with clamp_radius > 0 the far field is rescaled (Sec. III B).  Kernels are
+ * queued on `stream`; the run must not be stepped from two streams at once.
+ * LBM_EINVAL for a null run or nsteps < 0, LBM_ESTATE for a member of a
+ * batch (those advance with lbm_batch_step), LBM_EDEVICE on a launch
+ * failure.  async. */
 lbm_status lbm_step(lbm_run* run, int64_t nsteps, void* stream);
 
 /* Advance nsteps and measure the device time between HIP events recorded
@@ -174,7 +184,9 @@ lbm_status lbm_step_timed(lbm_run* run, int64_t nsteps, void* stream, double* ms
 int64_t lbm_step_count(const lbm_run* run);
 
 /* Density rho = sum_k f_k and velocity u = sum_k f_k xi_k / rho (no force
- * shift) of the current state into host arrays of Lx*Ly doubles.  sync. */
+ * shift; the moments of Eq. herfeq) of the current state into host arrays of
+ * Lx*Ly doubles, row-major (index j * Lx + i).  LBM_EINVAL for null
+ * arguments.  sync. */
 lbm_status lbm_moments(lbm_run* run, double* h_rho, double* h_ux, double* h_uy, void* stream);
 
 /* As lbm_moments into device arrays.  async. */
@@ -305,7 +317,7 @@ lbm_status lbm_batch_set_mode(lbm_batch* batch, int32_t mode, void* stream);
 int32_t lbm_batch_get_mode(const lbm_batch* batch);
 
 /* Bound, in polls, of each dependency wait of the persistent launch (0 =
- * the default, about a second).  A wait that exceeds it sets the batch's
+ * the default, 2^22 polls: several seconds).  A wait that exceeds it sets the batch's
  * error word and lets the launch finish with invalid results, so a launch
  * never hangs; lbm_batch_sync_status reports it.  Drops a captured graph.
  * sync. */

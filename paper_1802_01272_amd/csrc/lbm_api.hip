@@ -242,7 +242,8 @@ struct lbm_run {
 };
 
 // polls of one dependency wait of the persistent batched launch before it
-// gives up (about a second at ~0.3 us per poll; a correct launch waits at
+// gives up (a poll is a device-scope load and a short sleep, about 1-2 us, so
+// the default bounds a wait at several seconds; a correct launch waits at
 // most a few work items' time)
 constexpr uint32_t DEFAULT_WAIT_LIMIT = 1u << 22;
 
