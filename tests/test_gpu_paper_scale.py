@@ -71,7 +71,7 @@ def _pw(rho):
     return thermo.pressure(rho, T)
 
 
-@pytest.mark.parametrize("L,nsteps", [(4096, 700000), (6144, 700000)])
+@pytest.mark.parametrize("L,nsteps", [(4096, 700000), (6144, 650000)])
 def test_rp_growth(L, nsteps):
     import torch
     from paper_1802_01272_amd import inputs as I
