@@ -301,6 +301,17 @@ lbm_status lbm_batch_autotune(lbm_batch* batch, int32_t steps_per_trial, void* s
 
 /* Borrowed handle of run r (valid while the batch lives) for lbm_moments,
  * lbm_get_f, lbm_set_f and lbm_reduce; lbm_step on it is rejected. */
+/* The same two calls under the names of the survey's boundary: lbm_init_batch
+ * is lbm_batch_init; lbm_step_batch advances every run by nsteps, replaying a
+ * captured graph of LBM_BATCH_GRAPH_STEPS steps (lbm_batch_step with that
+ * graph_steps).  async. */
+enum { LBM_BATCH_GRAPH_STEPS = 20 };
+lbm_status lbm_init_batch(int32_t n, const lbm_params* params, void* d_ws, size_t ws_bytes,
+                          void* stream, const double* const* h_rho0,
+                          const double* const* h_ux0, const double* const* h_uy0,
+                          lbm_batch** out);
+lbm_status lbm_step_batch(lbm_batch* batch, int64_t nsteps, void* stream);
+
 /* How a batch advances (Sec. III: the paper's runs are independent lattices;
  * batching them is this library's own scheduling).
  * LBM_BATCH_PER_STEP (the default): one grouped launch per time step over

@@ -1124,6 +1124,18 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps, int32_t graph_steps, voi
     return LBM_OK;
 }
 
+lbm_status lbm_init_batch(int32_t n, const lbm_params* params, void* d_ws, size_t ws_bytes, void* stream,
+                          const double* const* h_rho0, const double* const* h_ux0, const double* const* h_uy0,
+                          lbm_batch** out)
+{
+    return lbm_batch_init(n, params, d_ws, ws_bytes, stream, h_rho0, h_ux0, h_uy0, out);
+}
+
+lbm_status lbm_step_batch(lbm_batch* b, int64_t nsteps, void* stream)
+{
+    return lbm_batch_step(b, nsteps, LBM_BATCH_GRAPH_STEPS, stream);
+}
+
 lbm_status lbm_batch_set_mode(lbm_batch* b, int32_t mode, void* stream)
 {
     if (!b) return fail(LBM_EINVAL, "null batch");

@@ -137,6 +137,9 @@ def _load():
         "lbm_batch_set_launch": ([vp, ctypes.c_int32, vp], st),
         "lbm_batch_autotune": ([vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)], st),
         "lbm_batch_run": ([vp, ctypes.c_int32], vp),
+        "lbm_init_batch": ([ctypes.c_int32, P, vp, ctypes.c_size_t, vp, ctypes.POINTER(D), ctypes.POINTER(D),
+                            ctypes.POINTER(D), ctypes.POINTER(vp)], st),
+        "lbm_step_batch": ([vp, ctypes.c_int64, vp], st),
         "lbm_batch_set_mode": ([vp, ctypes.c_int32, vp], st),
         "lbm_batch_get_mode": ([vp], ctypes.c_int32),
         "lbm_batch_set_wait_limit": ([vp, ctypes.c_uint32, vp], st),

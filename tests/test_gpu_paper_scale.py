@@ -94,7 +94,10 @@ def test_rp_growth(L, nsteps):
         st = run.reduce(0.5 * (rv + rl))
         ts.append(s * DT)
         Rs.append(st["R_eq"])
-        if s % (4 * every) == 0 or s == every:
+        # pressures every 5000 steps while the interface relaxes and the
+        # bubble sits near its critical radius (Eq. rp is sensitive to p_B -
+        # p_inf there), every 20000 steps after
+        if s <= 100000 or s % (4 * every) == 0:
             rho, _, _ = run.moments_device()
             centre = float(rho[c - 1:c + 1, c - 1:c + 1].mean())
             edge = float(rho.flatten()[ring_idx].mean())
@@ -106,6 +109,8 @@ def test_rp_growth(L, nsteps):
             print("L %d step %d: R %.4f (%.1f ds) p_B - p_inf %.4e  (%.0f s)"
                   % (L, s, Rs[-1], Rs[-1] / DS, pB[-1] - pinf[-1], time.time() - t0), flush=True)
     run.close()
+    _save("rp_%d_lb" % L, {"t": ts, "R": Rs, "t_p": tp, "p_B": pB, "p_inf": pinf, "R0_ds": R0,
+                           "rho_ext": rho_ext, "r_inf": r_bc * DS})
     ts, Rs = np.array(ts), np.array(Rs)
     tp, pB, pinf = np.array(tp), np.array(pB), np.array(pinf)
     # Eq. rp from the state after the interface has relaxed

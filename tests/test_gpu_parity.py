@@ -522,6 +522,26 @@ def test_persistent_batch_equals_single_runs(kinds, graph_steps, rows):
     batch.close()
 
 
+@pytest.mark.parametrize("scheme,reg", [(1, 0), (1, 1), (2, 1)])
+def test_persistent_batch_other_schemes(scheme, reg):
+    """The persistent launch's other instantiations (CTU1, regularized)
+    equal single runs bitwise over 70 steps, periodic and wall runs mixed."""
+    specs = [make_params(Lx, Ly, scheme=scheme, reg=reg, bc=bc, precision=1)
+             for Lx, Ly, bc in ((70, 50, 1), (33, 19, 0), (57, 66, 0))]
+    states = [random_state(p, 500 + i) for i, p in enumerate(specs)]
+    singles = [gpu_step_from(p, f, nsteps=70) for p, f in zip(specs, states)]
+    batch = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
+    batch.set_launch(8)
+    batch.set_mode(lbm.BATCH_PERSISTENT)
+    for m, f in zip(batch.runs, states):
+        m.set_f(f)
+    batch.step(70, graph_steps=10)
+    batch.sync_status()
+    for m, ref in zip(batch.runs, singles):
+        assert np.array_equal(m.get_f(), ref)
+    batch.close()
+
+
 def test_persistent_batch_reports_a_wait_past_its_bound():
     """A dependency wait that exceeds its bound ends the launch with an
     error instead of hanging: with a bound of one poll, the item of step 1
@@ -545,6 +565,39 @@ def test_persistent_batch_reports_a_wait_past_its_bound():
     batch.sync_status()
     assert np.array_equal(batch.runs[0].get_f(), gpu_step_from(p, f, nsteps=8, start_step=8))
     batch.close()
+
+
+def test_boundary_batch_aliases():
+    """lbm_step_batch (graph-replayed steps) equals lbm_batch_step, and
+    lbm_init_batch builds the same batch as lbm_batch_init."""
+    import ctypes
+    specs = [make_params(70, 50, bc=1, precision=1), make_params(33, 19, precision=1)]
+    states = [random_state(p, 400 + i) for i, p in enumerate(specs)]
+    a = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
+    b = lbm.Batch(specs, [(1.0, 0.0, 0.0)] * len(specs))
+    for x, y, f in zip(a.runs, b.runs, states):
+        x.set_f(f)
+        y.set_f(f)
+    a.step(45)
+    stream = ctypes.c_void_p(b.torch.cuda.current_stream().cuda_stream)
+    assert lbm.LIB.lbm_step_batch(b.handle, 45, stream) == lbm.LBM_OK
+    for x, y in zip(a.runs, b.runs):
+        assert y.step_count == 45
+        assert np.array_equal(x.get_f(), y.get_f())
+    a.close()
+    b.close()
+    n = len(specs)
+    cp = (lbm.CParams * n)(*[p.c() for p in specs])
+    ws = b.torch.empty(int(lbm.LIB.lbm_batch_workspace_bytes(n, cp)), dtype=b.torch.uint8, device="cuda")
+    arrs = [np.full((p.Ly, p.Lx), 1.1) for p in specs] + [np.zeros((p.Ly, p.Lx)) for p in specs]
+    P = ctypes.POINTER(ctypes.c_double)
+    rho = (P * n)(*[a_.ctypes.data_as(P) for a_ in arrs[:n]])
+    zero = (P * n)(*[a_.ctypes.data_as(P) for a_ in arrs[n:]])
+    h = ctypes.c_void_p()
+    assert lbm.LIB.lbm_init_batch(n, cp, ctypes.c_void_p(ws.data_ptr()), ws.numel(), stream, rho, zero, zero,
+                                  ctypes.byref(h)) == lbm.LBM_OK
+    assert lbm.LIB.lbm_step_batch(h, 2, stream) == lbm.LBM_OK
+    lbm.LIB.lbm_batch_destroy(h)
 
 
 def test_persistent_mode_needs_fp32():
