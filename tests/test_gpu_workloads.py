@@ -94,6 +94,41 @@ def test_quiescent_cavitation_1024_against_rayleigh_plesset():
     assert np.all(rel[i0:] > -0.005) and np.all(rel[i0:] < 0.35)
 
 
+def test_persistent_batch_equals_per_step_on_the_sweep():
+    """The persistent batched launch at the sweep's full scale (12 of its
+    runs, about 7 M nodes and 2,000 work items per step, more than the
+    device holds at once, so items of consecutive steps overlap across all
+    XCDs) against one launch per step from the same states, bit for bit
+    after 300 steps (graph-replayed), compared on the device."""
+    import torch
+    sweep = I.batched_sweep(32, seed=5)[:12]
+    params = [lbm.Params.from_workload(w, precision=lbm.FP32_DEV) for w in sweep]
+    fields = [w.fields() for w in sweep]
+    out = {}
+    for mode in (lbm.BATCH_PER_STEP, lbm.BATCH_PERSISTENT):
+        batch = lbm.Batch(params, fields)
+        batch.set_launch(32)
+        batch.set_mode(mode)
+        batch.step(300, graph_steps=20)
+        batch.sync_status()
+        res = []
+        for m, p in zip(batch.runs, params):
+            d = torch.empty(16 * p.Lx * p.Ly, dtype=torch.float64, device="cuda")
+            assert lbm.LIB.lbm_get_f_device(m.handle, ctypes_ptr(d), None) == lbm.LBM_OK
+            res.append(d)
+        torch.cuda.synchronize()
+        out[mode] = res
+        batch.close()
+    for a, b in zip(out[lbm.BATCH_PER_STEP], out[lbm.BATCH_PERSISTENT]):
+        assert bool(torch.isfinite(a).all())
+        assert torch.equal(a, b)
+
+
+def ctypes_ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def test_batched_sweep_smallest_runs_against_oracle():
     sweep = I.batched_sweep(32, seed=5)
     params = [lbm.Params.from_workload(w, precision=lbm.FP32_DEV) for w in sweep]
