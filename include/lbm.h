@@ -301,8 +301,8 @@ lbm_status lbm_batch_autotune(lbm_batch* batch, int32_t steps_per_trial, void* s
 
 /* Borrowed handle of run r (valid while the batch lives) for lbm_moments,
  * lbm_get_f, lbm_set_f and lbm_reduce; lbm_step on it is rejected. */
-/* The same two calls under the names of the survey's boundary: lbm_init_batch
- * is lbm_batch_init; lbm_step_batch advances every run by nsteps, replaying a
+/* Alternative names of the two batch calls: lbm_init_batch is
+ * lbm_batch_init; lbm_step_batch advances every run by nsteps, replaying a
  * captured graph of LBM_BATCH_GRAPH_STEPS steps (lbm_batch_step with that
  * graph_steps).  async. */
 enum { LBM_BATCH_GRAPH_STEPS = 20 };
