@@ -32,13 +32,13 @@ with open(os.path.join(HERE, "golden", "paper_values.json")) as fh:
 T, DS, DT, TAU, KAPPA, L = 0.8, 1.0 / 256, 1e-4, 1e-3, 1e-4, 1024
 
 
-def bubble_fate(rho_ext, R0, max_steps=400000, every=5000):
+def bubble_fate(rho_ext, R0, max_steps=400000, every=5000, tau=TAU):
     """+1 if a bubble of initial radius R0 nodes grows by 3 nodes, -1 if it
     shrinks by 3, 0 if neither within max_steps."""
     from paper_1802_01272_amd import inputs as I
     rv, rl = thermo.maxwell(T)
     rho = I.bubble(L, L, PAPER["coexistence_T0.8"]["rho_V"], rho_ext, R0, 4.0)
-    p = lbm.Params(Lx=L, Ly=L, ds=DS, dt=DT, tau=TAU, T=T, kappa=KAPPA, scheme=2, precision=lbm.FP64,
+    p = lbm.Params(Lx=L, Ly=L, ds=DS, dt=DT, tau=tau, T=T, kappa=KAPPA, scheme=2, precision=lbm.FP64,
                    clamp_radius=L / 2 - 0.5 / DS, clamp_rho=rho_ext)
     run = lbm.Run(p, rho, 0.0, 0.0)
     fate, s, r = 0, 0, R0
@@ -89,6 +89,16 @@ def test_critical_radius_bracket_at_lower_superheat():
     pred = thermo.critical_radius(T, rho_ext, sigma) / DS
     assert bubble_fate(rho_ext, int(math.floor(pred))) == -1
     assert bubble_fate(rho_ext, int(math.ceil(1.06 * pred))) == 1
+
+
+def test_critical_radius_of_the_sheared_runs():
+    """The initial radius of the sheared-bubble runs (Sec. III C: rho_ext =
+    1.90, tau = 1e-2, the paper's R = 26 ds grows there).  In this model 26 ds
+    shrinks and 27 ds grows at tau = 1e-2 (R_c 26.5 ds, 14% above Eq.
+    raggio_c's 23.2 ds), and 24 ds shrinks and 25 ds grows at tau = 1e-3; the
+    paper-scale sheared runs therefore start at 27 ds."""
+    assert bubble_fate(1.90, 26, tau=1e-2) == -1 and bubble_fate(1.90, 27, tau=1e-2) == 1
+    assert bubble_fate(1.90, 24) == -1 and bubble_fate(1.90, 25) == 1
 
 
 # --------------------------------------------------------------------------
