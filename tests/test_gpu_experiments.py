@@ -130,20 +130,21 @@ def shear_wave_nu(tau, ds, scheme, diagonal, reg, t_end, dt=1e-4, U=0.01):
 def test_regularization_restores_isotropy_ctu2():
     """CTU2 on ds = 1/256 (Fig. newfiguregg): at tau = 0.01 regularization
     changes nothing by t = 2 (within 1e-3; 6e-4 apart during the first half
-    time unit); for tau > 0.1 the unregularized axial and diagonal waves
-    decay differently (measured 16% and 12% apart at tau = 0.2, 0.3) while the
-    diagonal waves agree across ds; regularized, all agree (to 2e-4)."""
+    time unit); from tau = 0.1 on the unregularized axial and diagonal waves
+    decay differently (measured 2.4%, 16%, 12% and 2.4% apart at tau = 0.1,
+    0.2, 0.3 and 0.5) while the diagonal waves agree across ds; regularized,
+    all agree (to 2e-4)."""
     ds = 1.0 / 256
     a0, a1 = (shear_wave_nu(0.01, ds, 2, False, r, 2.0) for r in (0, 1))
     print("tau 0.01 axial: nu %.6e plain, %.6e regularized" % (a0, a1))
     assert a1 == pytest.approx(a0, rel=1e-3)
-    for tau in (0.2, 0.3):
+    for tau, apart in ((0.1, 0.015), (0.2, 0.1), (0.3, 0.08), (0.5, 0.015)):
         t = 2.0 / (tau * math.pi ** 2)
         ax0, dg0 = shear_wave_nu(tau, ds, 2, False, 0, t), shear_wave_nu(tau, ds, 2, True, 0, t)
         ax1, dg1 = shear_wave_nu(tau, ds, 2, False, 1, t), shear_wave_nu(tau, ds, 2, True, 1, t)
         print("tau %.1f: plain axial %.5f diagonal %.5f; regularized axial %.5f diagonal %.5f"
               % (tau, ax0, dg0, ax1, dg1))
-        assert abs(ax0 - dg0) / dg0 > 0.05
+        assert abs(ax0 - dg0) / dg0 > apart
         assert abs(ax1 - dg1) / dg1 < 1e-3
     t = 2.0 / (0.2 * math.pi ** 2)
     dg_fine = shear_wave_nu(0.2, ds / math.sqrt(2.0), 2, True, 0, t)
