@@ -4,8 +4,9 @@ UBSan (no GPU).
 * ``sanitize/host_check.cpp`` drives every validation, sizing and
   argument-rejection path of ``include/lbm.h`` that runs before any device
   work, against a build of the library whose host code carries the
-  sanitizers (its device code is compiled without optimisation, to keep the
-  build short; it never runs here).
+  sanitizers and the C++ library's checked containers (_GLIBCXX_ASSERTIONS;
+  its device code is compiled without optimisation, to keep the build
+  short; it never runs here).
 * ``sanitize/oracle_check.c`` runs every oracle entry point on small and
   ragged lattices (down to 1 x 1) with every option, built together with the
   oracle's source under the sanitizers.
@@ -48,12 +49,13 @@ def test_host_abi_under_address_and_ub_sanitizers(tmp_path):
     lib = str(tmp_path / "liblbm_san.so")
     _run([HIPCC, "--offload-arch=gfx950", "-O1", "-Xarch_device", "-O0", "-g0", "-std=c++17", "-fPIC",
           "-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-omit-frame-pointer",
-          "-Xarch_host", "-g",
+          "-Xarch_host", "-g", "-Xarch_host", "-D_GLIBCXX_ASSERTIONS",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(ROOT, "include"), "-I" + csrc, "-shared",
           os.path.join(csrc, "lbm_api.hip"), os.path.join(csrc, "lbm_kernels.hip"), "-o", lib])
     exe = str(tmp_path / "host_check")
     _run([CLANG, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+          "-D_GLIBCXX_ASSERTIONS",
           "-I" + os.path.join(ROOT, "include"), os.path.join(HERE, "sanitize", "host_check.cpp"),
           "-L" + str(tmp_path), "-llbm_san", "-Wl,-rpath," + str(tmp_path), "-o", exe])
     r = _run([exe], env=SAN_ENV, timeout=300)
