@@ -262,9 +262,10 @@ void lbm_destroy(lbm_run* run);
 
 /* ---------------------------------------------------------------------- */
 /* Batched runs: n independent runs of arbitrary sizes and parameters that
- * advance together, one grouped launch per time step over a shared work
- * list of (run, strip) items, the steps captured once in a HIP graph and
- * replayed.  All runs must share `precision`. */
+ * advance together over a shared work list of (run, strip, chunk) items,
+ * one grouped launch per time step or one persistent launch for many steps
+ * (lbm_batch_set_mode), the launches captured once in a HIP graph and
+ * replayed.  All runs must share `precision`, `scheme` and `regularize`. */
 
 size_t lbm_batch_workspace_bytes(int32_t n, const lbm_params* params);
 
@@ -287,10 +288,9 @@ lbm_status lbm_batch_set_launch(lbm_batch* batch, int32_t rows_per_wave, void* s
 /* Time candidate rows-per-item values on the batch itself and keep the
  * fastest: first one value for every run (10 candidates, in each launch
  * mode the batch can use: both for FP32 storage, whose mode is then set to
- * the faster one), then, for each
- * class of runs of one lattice shape and boundary condition (largest total
- * node count first), up to 4 other values for that class alone, kept when
- * they save more than 1%.  The choice for each class is remembered for the
+ * the faster one), then, for each class of runs of one lattice shape and
+ * boundary condition (largest total node count first), up to 4 other
+ * values for that class alone, kept when they save more than 1%.  The choice for each class is remembered for the
  * process: later lbm_batch_init calls start runs of the same shape,
  * precision, scheme, regularize and boundary from it.  *rows_per_wave
  * receives the common value of the first pass.  The trials advance every
@@ -299,8 +299,6 @@ lbm_status lbm_batch_set_launch(lbm_batch* batch, int32_t rows_per_wave, void* s
 lbm_status lbm_batch_autotune(lbm_batch* batch, int32_t steps_per_trial, void* stream,
                               int32_t* rows_per_wave);
 
-/* Borrowed handle of run r (valid while the batch lives) for lbm_moments,
- * lbm_get_f, lbm_set_f and lbm_reduce; lbm_step on it is rejected. */
 /* Alternative names of the two batch calls: lbm_init_batch is
  * lbm_batch_init; lbm_step_batch advances every run by nsteps, replaying a
  * captured graph of LBM_BATCH_GRAPH_STEPS steps (lbm_batch_step with that
@@ -328,10 +326,10 @@ lbm_status lbm_batch_set_mode(lbm_batch* batch, int32_t mode, void* stream);
 int32_t lbm_batch_get_mode(const lbm_batch* batch);
 
 /* Bound, in polls, of each dependency wait of the persistent launch (0 =
- * the default, 2^22 polls: several seconds).  A wait that exceeds it sets the batch's
- * error word and lets the launch finish with invalid results, so a launch
- * never hangs; lbm_batch_sync_status reports it.  Drops a captured graph.
- * sync. */
+ * the default, 2^22 polls: several seconds).  A wait that exceeds it sets
+ * the batch's error word and lets the launch finish with invalid results, so
+ * a launch never hangs; lbm_batch_sync_status reports it.  Drops a captured
+ * graph.  sync. */
 lbm_status lbm_batch_set_wait_limit(lbm_batch* batch, uint32_t polls, void* stream);
 
 /* Wait for `stream`, then report the batch's error word: LBM_EDEVICE (and
@@ -340,6 +338,8 @@ lbm_status lbm_batch_set_wait_limit(lbm_batch* batch, uint32_t polls, void* stre
  * LBM_OK otherwise.  sync. */
 lbm_status lbm_batch_sync_status(lbm_batch* batch, void* stream);
 
+/* Borrowed handle of run r (valid while the batch lives) for lbm_moments,
+ * lbm_get_f, lbm_set_f and lbm_reduce; lbm_step on it is rejected. */
 lbm_run* lbm_batch_run(lbm_batch* batch, int32_t r);
 
 void lbm_batch_destroy(lbm_batch* batch);
